@@ -1,0 +1,196 @@
+"""Problem descriptions and seeded synthetic inputs.
+
+This module holds parameter containers and seeded random draws only: no step
+of the method is computed here.  The test suite and the benchmark hand the same
+descriptions to the GPU library and to the CPU oracle; neither of those imports
+the other.
+
+Workloads (synthetic; the paper measures no public dataset):
+  * driven harmonic oscillator, 1D, 1024 points;
+  * modulated 2D trap, 1024 x 1024;
+  * soft-core 3D atom in a Gaussian-envelope pulse, 512^3 (the throughput
+    workload);
+  * a batch of 256 independent 2D driven traps with seeded sizes and drives;
+  * a Poisson stream of mixed 1D/2D/3D requests (serving).
+The Gaussian initial state follows Section 4.2 of the paper.
+"""
+from __future__ import annotations
+
+import dataclasses as dc
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+@dc.dataclass
+class Wave:
+    """f(t) = A0 + A1 * env(t) * trig(omega t + phase); see the `kind` list."""
+    kind: str = "const"  # const | sin | cos | gauss_cos | sin2_cos
+    A0: float = 0.0
+    A1: float = 0.0
+    omega: float = 0.0
+    phase: float = 0.0
+    tc: float = 0.0
+    tau: float = 1.0
+    ti: float = 0.0
+    tf: float = 1.0
+
+
+def const(v: float) -> Wave:
+    return Wave("const", A0=v)
+
+
+@dc.dataclass
+class Grid:
+    ndim: int
+    n: Sequence[int]
+    lo: Sequence[float]
+    hi: Sequence[float]
+    mass: float = 1.0
+    hbar: float = 1.0
+    dt: float = 0.01
+
+    def full_n(self) -> List[int]:
+        return [int(v) for v in self.n] + [1] * (3 - len(self.n))
+
+    def shape(self) -> tuple:
+        return tuple(self.full_n()[: self.ndim])
+
+    def points(self) -> int:
+        return int(np.prod(self.full_n()))
+
+
+@dc.dataclass
+class Potential:
+    """V(x,t) = c(t) + sum_d [a_d(t) x_d + b_d(t) x_d^2] + s(t) V0(x)."""
+    a: List[Wave] = dc.field(default_factory=lambda: [Wave(), Wave(), Wave()])
+    b: List[Wave] = dc.field(default_factory=lambda: [Wave(), Wave(), Wave()])
+    c: Wave = dc.field(default_factory=Wave)
+    s: Wave = dc.field(default_factory=Wave)
+    v0_kind: str = "none"  # none | softcore | morse
+    v0_par: Sequence[float] = (0.0, 0.0, 0.0, 0.0)
+
+
+@dc.dataclass
+class Gaussian:
+    center: Sequence[float]
+    sigma: Sequence[float]
+    k: Sequence[float]
+
+
+@dc.dataclass
+class Problem:
+    name: str
+    grid: Grid
+    pot: Potential
+    init: Gaussian
+    steps: int
+    precision: str = "c128"  # c128 | c64
+    t0: float = 0.0
+
+
+# --- named workloads ----------------------------------------------------------
+
+def driven_ho_1d(n: int = 1024, steps: int = 1000, precision: str = "c128") -> Problem:
+    """1D, hbar = m = 1, [-20, 20), V = x^2/2 - E0 x sin(omega t), E0 = 0.1,
+    omega = 1; Gaussian at -5, sigma 1, k 2; dt 0.01."""
+    g = Grid(1, [n], [-20.0], [20.0], dt=0.01)
+    p = Potential()
+    p.b[0] = const(0.5)
+    p.a[0] = Wave("sin", A0=0.0, A1=-0.1, omega=1.0)
+    return Problem("driven_ho_1d", g, p, Gaussian([-5.0], [1.0], [2.0]), steps, precision)
+
+
+def modulated_trap_2d(n: int = 1024, steps: int = 2000, precision: str = "c128",
+                      half_width: float = 32.0) -> Problem:
+    """2D on [-32, 32)^2, V = (1 + 0.3 cos 2t) x^2/2 + (1 - 0.3 cos 2t) y^2/2;
+    Gaussian at (3, -2), sigma 1, k (0, 1); dt 0.005."""
+    g = Grid(2, [n, n], [-half_width] * 2, [half_width] * 2, dt=0.005)
+    p = Potential()
+    p.b[0] = Wave("cos", A0=0.5, A1=0.15, omega=2.0)
+    p.b[1] = Wave("cos", A0=0.5, A1=-0.15, omega=2.0)
+    return Problem("modulated_trap_2d", g, p, Gaussian([3.0, -2.0], [1.0, 1.0], [0.0, 1.0]),
+                   steps, precision)
+
+
+def softcore_3d(n: int = 512, steps: int = 2000, precision: str = "c64",
+                half_width: float = 40.0) -> Problem:
+    """3D on [-40, 40)^3, V = -1/sqrt(r^2 + 1) + E(t) z,
+    E(t) = 0.05 exp(-((t - 10)/4)^2) cos(1.5 t); Gaussian sigma 1 at the
+    origin, k = 0; dt 0.01."""
+    g = Grid(3, [n, n, n], [-half_width] * 3, [half_width] * 3, dt=0.01)
+    p = Potential(v0_kind="softcore", v0_par=(1.0, 1.0, 0.0, 0.0))
+    p.s = const(1.0)
+    p.a[2] = Wave("gauss_cos", A0=0.0, A1=0.05, omega=1.5, tc=10.0, tau=4.0)
+    return Problem("softcore_3d", g, p, Gaussian([0.0] * 3, [1.0] * 3, [0.0] * 3), steps, precision)
+
+
+def driven_trap(ndim: int, n: int, E0: float, omega: float, center, k, steps: int,
+                precision: str = "c64", half_width: float = 16.0, dt: float = 0.01) -> Problem:
+    """V = |x|^2/2 - E0 x sin(omega t) on [-16, 16)^ndim (batch and serving)."""
+    g = Grid(ndim, [n] * ndim, [-half_width] * ndim, [half_width] * ndim, dt=dt)
+    p = Potential()
+    for d in range(ndim):
+        p.b[d] = const(0.5)
+    p.a[0] = Wave("sin", A0=0.0, A1=-float(E0), omega=float(omega))
+    return Problem(f"driven_trap_{ndim}d_{n}", g, p,
+                   Gaussian(list(center), [1.0] * ndim, list(k)), steps, precision)
+
+
+def batch_2d(count: int = 256, seed: int = 1306, steps: int = 1000,
+             sizes: Sequence[int] = (128, 256, 512), precision: str = "c64") -> List[Problem]:
+    """Independent 2D driven traps: size uniform in `sizes`, E0 ~ U[0.01, 0.2],
+    omega ~ U[0.5, 2], centre ~ U[-3, 3]^2, k ~ U[-1, 1]^2, sigma 1 (drawn in
+    that order per solve from numpy's default_rng(seed))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(sizes))
+        E0 = float(rng.uniform(0.01, 0.2))
+        omega = float(rng.uniform(0.5, 2.0))
+        c = rng.uniform(-3.0, 3.0, size=2)
+        k = rng.uniform(-1.0, 1.0, size=2)
+        out.append(driven_trap(2, n, E0, omega, c, k, steps, precision))
+    return out
+
+
+@dc.dataclass
+class Request:
+    rid: int
+    arrival: float  # seconds after the stream starts
+    problem: Problem
+
+
+def serving_stream(count: int, rate_hz: float, seed: int = 1306,
+                   max_1d_log2: int = 13, max_3d: int = 256,
+                   steps_range=(500, 5000), precision: str = "c64") -> List[Request]:
+    """Poisson arrivals at `rate_hz`; mix 60% 1D (n = 2^k, k in [10, max_1d_log2]),
+    30% 2D (n in {128, 256, 512, 1024}), 10% 3D (n in {64, 128, max_3d}), each a
+    driven trap with E0 ~ U[0.01, 0.2], omega ~ U[0.5, 2], seeded Gaussian and
+    a step count uniform in steps_range."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate_hz))
+        u = float(rng.uniform())
+        if u < 0.6:
+            ndim, n = 1, 1 << int(rng.integers(10, max_1d_log2 + 1))
+        elif u < 0.9:
+            ndim, n = 2, int(rng.choice([128, 256, 512, 1024]))
+        else:
+            ndim, n = 3, int(rng.choice([s for s in (64, 128, 256) if s <= max_3d]))
+        E0 = float(rng.uniform(0.01, 0.2))
+        omega = float(rng.uniform(0.5, 2.0))
+        c = rng.uniform(-3.0, 3.0, size=ndim)
+        k = rng.uniform(-1.0, 1.0, size=ndim)
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        half = 20.0 if ndim == 1 else 16.0
+        reqs.append(Request(i, t, driven_trap(ndim, n, E0, omega, c, k, steps, precision, half)))
+    return reqs
+
+
+def random_state(shape, seed: int) -> np.ndarray:
+    """Seeded complex normal test state (no normalisation)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
