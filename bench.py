@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the split-operator step on one MI355X.
+
+Workload: the 3D soft-core atom in a pulse, 512^3 points on [-40, 40)^3,
+V = -1/sqrt(r^2 + 1) + E(t) z, E(t) = 0.05 exp(-((t-10)/4)^2) cos(1.5 t),
+Gaussian start (sigma 1 at the origin), dt = 0.01, FP32 state with FP64 phase
+arguments.  One bench step = one full time step of that grid (four line
+passes in the steady state).  The state is resident in HBM when timing starts.
+
+Prints one JSON line: site-steps/s of the FP32 path, the FP64 path beside it,
+the roofline of the dominant kernel (device time from HIP events around each
+launch), the FP32-vs-FP64 error of the run, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "site-steps/s at 3D 512³ FP32 vs FP64; p50/p99 latency of served solves"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ("paper_1306_3247_amd/csrc/wp_kernels.hip", "paper_1306_3247_amd/csrc/wp_device.hpp",
+                  "paper_1306_3247_amd/csrc/wp_internal.hpp")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kind: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    e = t.get("entries", {}).get(f"{workload}:{kind}")
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def time_gpu(sim_mod, prob, precision, steps, warmup):
+    import torch
+
+    stream = torch.cuda.current_stream()
+    s = sim_mod.from_problem(prob, precision=precision, stream=stream)
+    s.propagate(warmup)
+    s.synchronize()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    start.record(stream)
+    s.propagate(steps)
+    end.record(stream)
+    end.synchronize()
+    wall = time.perf_counter() - w0
+    torch.cuda.synchronize()
+    return s, start.elapsed_time(end), wall
+
+
+def cpu_baseline(prob, budget_s: float):
+    import oracle
+
+    g = prob.grid
+    psi = oracle.gaussian(g, prob.init.center, prob.init.sigma, prob.init.k)
+    steps, elapsed = 0, 0.0
+    while steps == 0 or elapsed < budget_s * 0.5:
+        t0 = time.perf_counter()
+        psi = oracle.propagate(g, prob.pot, psi, 1, t0=prob.t0, n0=steps)
+        elapsed += time.perf_counter() - t0
+        steps += 1
+    return {"value": g.points() * steps / elapsed, "unit": "site-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} step(s) of the same {'x'.join(map(str, g.shape()))} workload in FP64 "
+                      f"from the Gaussian start, {elapsed:.1f} s wall"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=512, help="points per axis")
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1306_3247_amd import sim as S
+    from paper_1306_3247_amd import workloads as W
+
+    prob = W.softcore_3d(n=args.n, precision="c64")
+    workload = f"softcore_3d_{args.n}"
+    sites = prob.grid.points()
+
+    s32, ms32, wall32 = time_gpu(S, prob, "c64", args.steps, args.warmup)
+    value = sites * args.steps / (ms32 / 1e3)
+    out = {"metric": METRIC, "value": value, "unit": "site-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms32 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": workload, "grid": list(prob.grid.shape()), "box": [-40.0, 40.0],
+                      "dt": prob.grid.dt, "state": "complex64", "phase_args": "f64"},
+           "wall_s_timed": round(wall32, 4)}
+
+    if not args.no_fp64:
+        # Same start, same number of steps, FP64 state: the FP32 error of this run.
+        s64, ms64, _ = time_gpu(S, prob, "c128", args.steps, args.warmup)
+        a = torch.view_as_real(s32.buffer.view(torch.complex64)).double()
+        b = torch.view_as_real(s64.buffer.view(torch.complex128))
+        rel = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        n32 = s32.observables(1)["norm"]
+        n64 = s64.observables(1)["norm"]
+        out["fp64"] = {"value": sites * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
+                       "dtype": "f64"}
+        out["accuracy"] = {"steps": args.warmup + args.steps, "rel_l2_f32_vs_f64": rel,
+                           "norm_drift_f32": abs(n32 - 1.0), "norm_drift_f64": abs(n64 - 1.0)}
+        s64.close()
+
+    # Roofline of the dominant kernel: every pass reads and writes the whole
+    # state once, so its algorithmic bytes per launch are 2 * state bytes.
+    prof = s32.profile_propagate(args.profile_steps)
+    kind, (cnt, tot) = max(prof.items(), key=lambda kv: kv[1][1])
+    state_bytes = S.state_bytes(prob.grid, "c64")
+    alg_bytes = 2 * state_bytes
+    avg_ms = tot / cnt
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": f"pass:{kind}", "achieved": round(achieved, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": traffic_for(kind, workload), "avg_launch_ms": round(avg_ms, 4),
+                       "alg_bytes_per_launch": alg_bytes,
+                       "passes": {k: {"launches": c, "avg_ms": round(m / c, 4)} for k, (c, m) in prof.items()}}
+    # Whole-step view against the 4-pass byte model (64 B per site-step).
+    step_gbs = 4 * alg_bytes * args.steps / (ms32 / 1e3) / 1e9
+    out["step_roofline"] = {"model": "4 passes x (read+write) per step", "achieved": round(step_gbs, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+    s32.close()
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W.softcore_3d(n=args.n, precision="c128"), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,230 @@
+/*
+ * wavepacket.h -- C ABI of libwavepacket, a split-operator solver of the
+ * time-dependent Schroedinger equation for one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Dion, Hashemloo, Rahali, "Program for quantum wave-packet dynamics
+ * with time-dependent potentials", Comput. Phys. Commun.  Section 2.1 gives
+ * the Hamiltonian H = P^2/2m + V(x,t) (eqs. tdse, hamiltonian), the
+ * short-time propagator (eq. short-time), its split form (eq. splitop), the
+ * grid (eqs. grid, Deltax), the FFT diagonalisation of the kinetic operator
+ * (eq. ft) and the momentum grid; Section 3.2 the user interface this ABI
+ * replaces (struct `parameters`, `potential`, `initialize_wf`, `norm`,
+ * `expectation1D`, `integrate3D`); Table 3 the observables.
+ *
+ * One time step, in the default order, is
+ *     psi <- exp(-i V(x,t_n+1) dt/2hbar) F^-1 exp(-i hbar|k|^2 dt/2m) F
+ *            exp(-i V(x,t_n) dt/2hbar) psi,        t_n = t0 + n dt,
+ * the Strang splitting with the potential integral of eq. short-time taken by
+ * the trapezoid rule.  Consecutive equal-time potential halves are merged on
+ * the device; the result equals the unmerged product up to rounding.
+ *
+ * Conventions shared by every entry point
+ *   - Grid: axis d has n[d] points, a power of two >= 2, on the half-open
+ *     interval [lo[d], hi[d]) with spacing (hi-lo)/n and x_i = lo + i*spacing.
+ *     1D problems lie along x and 2D problems in the xy-plane (Section 2.2);
+ *     unused axes have n = 1.  Boundaries are periodic.
+ *   - State psi: row-major [n0][n1][n2] (last axis contiguous), interleaved
+ *     (re, im).  WP_C128 stores two doubles per point, WP_C64 two floats.
+ *     The FP32 path keeps phase arguments, coordinates, time and every
+ *     reduction in FP64 and multiplies by FP64-accurate factors.
+ *   - Streams: all device work of a handle is ordered on the HIP stream
+ *     given at creation (NULL = the default stream).  Calls marked
+ *     "synchronises" wait for that stream before returning.
+ *   - Ownership: host buffers passed in are read or written during the call
+ *     only and stay owned by the caller.  Device buffers are owned by the
+ *     library unless bound with wp_bind_state.
+ *   - Errors: functions return a wp_status and never abort the process (the
+ *     paper's `abort` of Section 3.2 has no counterpart).  On failure the
+ *     handle keeps its previous state and wp_last_error describes the cause.
+ *   - Threads: a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef WAVEPACKET_H
+#define WAVEPACKET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WP_OK = 0,
+  WP_EINVAL = -1,       /* invalid argument or descriptor                     */
+  WP_ENOMEM = -2,       /* device or host allocation failed                   */
+  WP_EDEVICE = -3,      /* a HIP call failed                                  */
+  WP_EUNSUPPORTED = -4, /* valid input outside what this build implements     */
+  WP_ESTATE = -5        /* call not allowed in the handle's current state     */
+} wp_status;
+
+typedef enum { WP_C64 = 1, WP_C128 = 2 } wp_precision;
+
+/* Operator order of a step.  WP_ORDER_VKV is the default described above.
+ * WP_ORDER_KVK is eq. splitop as printed: kinetic half step, potential at the
+ * midpoint t_n + dt/2 over a full step, kinetic half step. */
+typedef enum { WP_ORDER_VKV = 0, WP_ORDER_KVK = 1 } wp_order;
+
+/* Scalar waveform f(t). */
+typedef enum {
+  WP_WAVE_CONST = 0,     /* A0                                                 */
+  WP_WAVE_SIN = 1,       /* A0 + A1 sin(omega t + phase)                       */
+  WP_WAVE_COS = 2,       /* A0 + A1 cos(omega t + phase)                       */
+  WP_WAVE_GAUSS_COS = 3, /* A0 + A1 exp(-((t - tc)/tau)^2) cos(omega t + phase) */
+  WP_WAVE_SIN2_COS = 4   /* A0 + A1 sin^2(pi (t-ti)/(tf-ti)) cos(omega t+phase) */
+                         /* on ti <= t <= tf, A0 elsewhere (the pulse of        */
+                         /* Section 4.1)                                        */
+} wp_wave_kind;
+
+typedef enum {
+  WP_V0_NONE = 0,
+  WP_V0_SOFTCORE = 1, /* -Z / sqrt(r^2 + eps2), r^2 over the used axes; par = {Z, eps2} */
+  WP_V0_MORSE = 2     /* D (1 - exp(-a (x - xe)))^2 along x (Section 4.1); par = {D, a, xe} */
+} wp_v0_kind;
+
+typedef struct {
+  int32_t kind; /* wp_wave_kind */
+  double A0, A1, omega, phase, tc, tau, ti, tf;
+} wp_waveform;
+
+/* Grid and physical constants (the grid, mass, dt and hbar fields of the
+ * paper's struct `parameters`, Section 3.2.1).  dt may be negative. */
+typedef struct {
+  int32_t ndim; /* 1, 2 or 3 */
+  int32_t prec; /* wp_precision of the device state */
+  uint64_t n[3];
+  double lo[3], hi[3];
+  double mass, hbar, dt;
+} wp_grid_desc;
+
+/* Potential family evaluated on the device at every step (replaces the user
+ * function `potential`, Section 3.2.3):
+ *   V(x,t) = c(t) + sum_d [a_d(t) x_d + b_d(t) x_d^2] + s(t) V0(x).
+ * Terms on unused axes are ignored.  This family holds every potential of
+ * Section 4 (Morse plus linear dipole coupling; the Paul trap quadrupole). */
+typedef struct {
+  wp_waveform a[3], b[3], c, s;
+  int32_t v0_kind; /* wp_v0_kind */
+  double v0_par[4];
+} wp_potential_desc;
+
+typedef struct wp_sim wp_sim;
+
+/* Bit mask of wp_observables; the output array holds 8 doubles in this order. */
+enum {
+  WP_OBS_NORM = 1u << 0,   /* sqrt(<psi|psi>)               (`norm`)          */
+  WP_OBS_X = 1u << 1,      /* <psi|x|psi>, not normalised    (`expectation1D`) */
+  WP_OBS_Y = 1u << 2,
+  WP_OBS_Z = 1u << 3,
+  WP_OBS_X2 = 1u << 4,     /* <psi|x^2|psi>                                    */
+  WP_OBS_Y2 = 1u << 5,
+  WP_OBS_Z2 = 1u << 6,
+  WP_OBS_ENERGY = 1u << 7, /* <psi|K + V(t)|psi>, K spectral (Table 3 energy)  */
+  WP_OBS_ALL = 0xffu
+};
+
+/* Device bytes of the state for this grid (n0*n1*n2 * 8 or 16).
+ * WP_EINVAL for an invalid descriptor. */
+wp_status wp_state_bytes(const wp_grid_desc *grid, uint64_t *bytes);
+
+/* Device bytes wp_create allocates for this grid in total, state included
+ * (state, per-axis kinetic and twiddle tables).  An energy request later
+ * adds one more state-sized scratch buffer.  Used for admission by HBM
+ * budget (the memory estimate of Section 3.5). */
+wp_status wp_workspace_bytes(const wp_grid_desc *grid, uint64_t *bytes);
+
+/* Create a solver on the current HIP device for the grid and potential (the
+ * set-up of `initialize_potential`, Section 3.2.2).  `stream` is a
+ * hipStream_t or NULL.  The state is zero and the time 0 until a set_state
+ * call; the state buffer itself is allocated on first use unless one is
+ * bound with wp_bind_state.  Errors: WP_EINVAL (bad descriptor: ndim not in 1..3, n not a power of
+ * two or < 2 on a used axis, n != 1 on an unused axis, hi <= lo, mass <= 0,
+ * hbar <= 0, dt = 0 or not finite, unknown kinds), WP_EUNSUPPORTED (an axis
+ * longer than this build's line FFT: 8192 points for 1D, 4096 for 2D/3D),
+ * WP_ENOMEM, WP_EDEVICE.  On success *out owns all device buffers. */
+wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void *stream,
+                    wp_sim **out);
+
+/* Release every library-owned buffer.  Waits for the handle's stream. */
+wp_status wp_destroy(wp_sim *sim);
+
+/* Use caller-owned device memory `dev_psi` (at least wp_state_bytes, 16-byte
+ * aligned) as the state from now on; a state buffer the library allocated
+ * before is freed.
+ * The caller keeps ownership and must keep the memory alive until
+ * wp_destroy.  The content is not changed.  Errors: WP_EINVAL (NULL, too
+ * small or misaligned). */
+wp_status wp_bind_state(wp_sim *sim, void *dev_psi, uint64_t bytes);
+
+/* Device pointer of the current state (library-owned or bound). */
+void *wp_state_ptr(wp_sim *sim);
+
+/* Copy a host state (row-major, complex128, n0*n1*n2 points) to the device,
+ * converting to the handle's precision, and set the time origin: after this
+ * call the state is psi(t0) and the step counter is 0 (the role of
+ * `initialize_wf`, Section 3.2.4).  Synchronises. */
+wp_status wp_set_state(wp_sim *sim, const double *host_psi_c128, double t0);
+
+/* Set psi(t0) to the Gaussian of Section 4.2,
+ *   prod_d (2/pi)^(1/4) sigma_d^(-1/2) exp(-(x_d-c_d)^2/sigma_d^2 + i k_d (x_d-c_d)),
+ * renormalised to unit discrete norm (k_d = p_d0/hbar).  Arrays hold one
+ * entry per axis (3 entries; unused axes ignored).  sigma_d must be > 0. */
+wp_status wp_set_state_gaussian(wp_sim *sim, const double center[3], const double sigma[3],
+                                const double k[3], double t0);
+
+/* Advance the state by nsteps steps of dt (Algorithm 1's inner loop with
+ * merged equal-time potential halves).  Asynchronous on the handle's stream;
+ * nsteps = 0 is a no-op.  The step counter advances by nsteps. */
+wp_status wp_propagate(wp_sim *sim, uint64_t nsteps);
+
+/* Select the operator order used by later wp_propagate calls (default
+ * WP_ORDER_VKV).  WP_EINVAL for an unknown order. */
+wp_status wp_set_order(wp_sim *sim, int32_t order);
+
+/* Copy the state at the current time to host memory as interleaved
+ * complex128 (as_prec = WP_C128) or complex64 (WP_C64).  Synchronises. */
+wp_status wp_get_state(wp_sim *sim, void *host_out, int32_t as_prec);
+
+/* FP64 observables of the current state at the current time (Table 3 and
+ * the `norm` / `expectation1D` utilities of Section 3.2.6): writes the 8
+ * values in the WP_OBS_* order into out[8]; entries not in `mask` are 0.
+ * Integrals use the rectangle rule over the periodic cell.  Deterministic
+ * (fixed reduction order).  Synchronises. */
+wp_status wp_observables(wp_sim *sim, uint32_t mask, double *out);
+
+/* Kernel classes of a propagation, for wp_profile_propagate. */
+enum {
+  WP_PASS_SOLVE1D = 0,  /* whole 1D solve in one workgroup                    */
+  WP_PASS_AXIS0 = 1,    /* first axis: inverse FFT, potential phase, FFT       */
+  WP_PASS_MID_FWD = 2,  /* middle axis (3D): forward FFT                       */
+  WP_PASS_LAST = 3,     /* last axis: FFT, kinetic phase, inverse FFT          */
+  WP_PASS_MID_INV = 4,  /* middle axis (3D): inverse FFT                       */
+  WP_PASS_EDGE = 5,     /* first-axis pass opening or closing a propagation    */
+  WP_PASS_KINDS = 6
+};
+
+/* Same work as wp_propagate(sim, nsteps) (the state advances identically),
+ * with a HIP event pair around every kernel launch on the handle's stream.
+ * On return ms[k] holds the summed device time (milliseconds) and count[k]
+ * the number of launches of kernel class k, for k < WP_PASS_KINDS (arrays of
+ * at least WP_PASS_KINDS entries, caller-owned).  Synchronises.  Meant for
+ * measurement: the events add a small gap between launches.  nsteps must be
+ * in 1..100000 (WP_EINVAL otherwise). */
+wp_status wp_profile_propagate(wp_sim *sim, uint64_t nsteps, double *ms, uint64_t *count);
+
+/* Current time t0 + steps*dt and step counter. */
+wp_status wp_get_time(wp_sim *sim, double *t, uint64_t *step);
+
+/* Wait for all work queued by this handle. */
+wp_status wp_synchronize(wp_sim *sim);
+
+/* Human-readable description of the last error on this handle (never NULL;
+ * "" when none).  Valid until the next call on the handle. */
+const char *wp_last_error(const wp_sim *sim);
+
+/* Library version string. */
+const char *wp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,668 @@
+// wp_capi.cpp -- C ABI of libwavepacket: argument checking, per-axis tables,
+// the pass schedule of a step, and observables.  See include/wavepacket.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/wavepacket.h"
+#include "wp_internal.hpp"
+
+using wp::cx;
+
+struct wp_sim {
+  wp_grid_desc g{};
+  wp_potential_desc p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int lg[3] = {0, 0, 0};
+  int64_t total = 0;
+  int prec = 2;
+  void *psi = nullptr;
+  bool psi_owned = false;
+  uint64_t psi_bytes = 0;
+  void *scratch = nullptr;  // momentum-space copy for the energy
+  cx<double> *d_kfull = nullptr, *d_khalf = nullptr;  // n0+n1+n2 entries each
+  double *d_k2 = nullptr;                              // k^2 per axis, n0+n1+n2
+  cx<double> *d_tw[3] = {nullptr, nullptr, nullptr};
+  double *d_partials = nullptr, *d_out8 = nullptr;
+  int obs_blocks = 1;
+  double t0 = 0.0;
+  uint64_t step = 0;
+  int32_t order = WP_ORDER_VKV;
+  wp::GridDev gd{};
+  wp::PotDev pd{};
+  std::string err;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+bool is_pow2(uint64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
+int ilog2(uint64_t n) {
+  int l = 0;
+  while ((uint64_t(1) << l) < n) ++l;
+  return l;
+}
+
+wp_status fail(wp_sim *s, wp_status code, const std::string &msg) {
+  if (s) s->err = msg;
+  return code;
+}
+
+wp_status hip_fail(wp_sim *s, hipError_t e, const char *what) {
+  return fail(s, WP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool wave_ok(const wp_waveform &w) {
+  if (w.kind < WP_WAVE_CONST || w.kind > WP_WAVE_SIN2_COS) return false;
+  const double v[] = {w.A0, w.A1, w.omega, w.phase, w.tc, w.tau, w.ti, w.tf};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  if (w.kind == WP_WAVE_GAUSS_COS && w.tau == 0.0) return false;
+  if (w.kind == WP_WAVE_SIN2_COS && !(w.tf > w.ti)) return false;
+  return true;
+}
+
+// Returns an empty string when the descriptor is valid.
+std::string check_grid(const wp_grid_desc *g) {
+  if (!g) return "grid descriptor is NULL";
+  if (g->ndim < 1 || g->ndim > 3) return "ndim must be 1, 2 or 3";
+  if (g->prec != WP_C64 && g->prec != WP_C128) return "prec must be WP_C64 or WP_C128";
+  for (int d = 0; d < 3; ++d) {
+    if (d < g->ndim) {
+      if (g->n[d] < 2 || !is_pow2(g->n[d])) return "n on a used axis must be a power of two >= 2";
+      if (!std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]) || !(g->hi[d] > g->lo[d]))
+        return "each used axis needs finite lo < hi";
+    } else if (g->n[d] != 1) {
+      return "unused axes must have n = 1";
+    }
+  }
+  if (!(g->mass > 0) || !std::isfinite(g->mass)) return "mass must be finite and > 0";
+  if (!(g->hbar > 0) || !std::isfinite(g->hbar)) return "hbar must be finite and > 0";
+  if (!(g->dt != 0) || !std::isfinite(g->dt)) return "dt must be finite and nonzero";
+  return "";
+}
+
+std::string check_pot(const wp_potential_desc *p) {
+  if (!p) return "potential descriptor is NULL";
+  for (int d = 0; d < 3; ++d)
+    if (!wave_ok(p->a[d]) || !wave_ok(p->b[d])) return "invalid waveform in a[] or b[]";
+  if (!wave_ok(p->c) || !wave_ok(p->s)) return "invalid waveform c or s";
+  if (p->v0_kind < WP_V0_NONE || p->v0_kind > WP_V0_MORSE) return "unknown v0_kind";
+  for (double x : p->v0_par)
+    if (!std::isfinite(x)) return "v0_par must be finite";
+  return "";
+}
+
+std::string check_supported(const wp_grid_desc *g) {
+  if (g->ndim == 1) {
+    if (g->n[0] > (uint64_t)wp::kMaxLine1D) return "1D grids are limited to 8192 points in this build";
+  } else {
+    for (int d = 0; d < g->ndim; ++d)
+      if (g->n[d] > (uint64_t)wp::kMaxLinePass) return "2D/3D axes are limited to 4096 points in this build";
+  }
+  return "";
+}
+
+double spacing(const wp_grid_desc &g, int d) { return (g.hi[d] - g.lo[d]) / (double)g.n[d]; }
+
+// Wavenumber of DFT bin m (Section 2.1 momentum grid, k = p/hbar): m for
+// m < n/2, m - n otherwise.
+double wavenumber(const wp_grid_desc &g, int d, uint64_t m) {
+  const int64_t n = (int64_t)g.n[d];
+  const int64_t mm = ((int64_t)m < n / 2) ? (int64_t)m : (int64_t)m - n;
+  return 2.0 * kPi * (double)mm / ((double)n * spacing(g, d));
+}
+
+wp::WaveDev to_dev(const wp_waveform &w) {
+  wp::WaveDev d;
+  d.kind = w.kind;
+  d.A0 = w.A0; d.A1 = w.A1; d.omega = w.omega; d.phase = w.phase;
+  d.tc = w.tc; d.tau = w.tau; d.ti = w.ti; d.tf = w.tf;
+  return d;
+}
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+uint64_t table_bytes(const wp_grid_desc &g) {
+  uint64_t axes = g.n[0] + g.n[1] + g.n[2];
+  return axes * (16 + 16 + 8 + 16) + 1024 * 8 * 8 + 64;
+}
+
+void release(wp_sim *s) {
+  if (s->psi_owned && s->psi) (void)hipFree(s->psi);
+  if (s->scratch) (void)hipFree(s->scratch);
+  if (s->d_kfull) (void)hipFree(s->d_kfull);
+  if (s->d_khalf) (void)hipFree(s->d_khalf);
+  if (s->d_k2) (void)hipFree(s->d_k2);
+  for (auto &p : s->d_tw)
+    if (p) (void)hipFree(p);
+  if (s->d_partials) (void)hipFree(s->d_partials);
+  if (s->d_out8) (void)hipFree(s->d_out8);
+}
+
+// The state buffer is allocated on first use unless the caller bound one.
+hipError_t ensure_state(wp_sim *s) {
+  if (s->psi) return hipSuccess;
+  hipError_t e = hipMalloc(&s->psi, s->psi_bytes);
+  if (e != hipSuccess) {
+    s->psi = nullptr;
+    return e;
+  }
+  s->psi_owned = true;
+  return hipMemsetAsync(s->psi, 0, s->psi_bytes, s->stream);
+}
+
+wp_status state_fail(wp_sim *s, hipError_t e, const char *what) {
+  return e == hipErrorOutOfMemory ? fail(s, WP_ENOMEM, std::string(what) + ": out of device memory")
+                                  : hip_fail(s, e, what);
+}
+
+wp::PassArgs pass_args(const wp_sim *s, int axis, uint32_t ops) {
+  wp::PassArgs a{};
+  a.psi = s->psi;
+  a.g = s->gd;
+  a.axis = axis;
+  int lgi = 0;
+  for (int d = axis + 1; d < 3; ++d) lgi += s->lg[d];
+  a.lg_inner = lgi;
+  a.n_lines = s->total >> s->lg[axis];
+  a.ops = ops;
+  a.time.t0 = s->t0;
+  a.time.dt = s->g.dt;
+  a.time.step = 0;
+  a.time.step_dev = nullptr;
+  a.time.half = 0.0;
+  a.vtau = 0.0;
+  a.pot = s->pd;
+  int off = 0;
+  for (int d = 0; d < 3; ++d) {
+    a.ktab[d] = s->d_kfull + off;
+    off += (int)s->g.n[d];
+  }
+  a.tw = s->d_tw[axis];
+  return a;
+}
+
+void use_half_kinetic(const wp_sim *s, wp::PassArgs &a) {
+  int off = 0;
+  for (int d = 0; d < 3; ++d) {
+    a.ktab[d] = s->d_khalf + off;
+    off += (int)s->g.n[d];
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wp_version(void) { return "wavepacket-gfx950 0.1"; }
+
+const char *wp_last_error(const wp_sim *sim) { return sim ? sim->err.c_str() : "NULL handle"; }
+
+wp_status wp_state_bytes(const wp_grid_desc *grid, uint64_t *bytes) {
+  if (!bytes || !check_grid(grid).empty()) return WP_EINVAL;
+  const uint64_t elem = grid->prec == WP_C64 ? 8 : 16;
+  *bytes = grid->n[0] * grid->n[1] * grid->n[2] * elem;
+  return WP_OK;
+}
+
+wp_status wp_workspace_bytes(const wp_grid_desc *grid, uint64_t *bytes) {
+  uint64_t st = 0;
+  if (wp_state_bytes(grid, &st) != WP_OK) return WP_EINVAL;
+  *bytes = st + table_bytes(*grid);
+  return WP_OK;
+}
+
+wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void *stream, wp_sim **out) {
+  if (!out) return WP_EINVAL;
+  *out = nullptr;
+  if (!check_grid(grid).empty() || !check_pot(pot).empty()) return WP_EINVAL;
+  if (!check_supported(grid).empty()) return WP_EUNSUPPORTED;
+  wp_sim *s = new (std::nothrow) wp_sim();
+  if (!s) return WP_ENOMEM;
+  s->g = *grid;
+  s->p = *pot;
+  s->stream = (hipStream_t)stream;
+  s->prec = grid->prec;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) {
+    delete s;
+    return WP_EDEVICE;
+  }
+  s->total = 1;
+  for (int d = 0; d < 3; ++d) {
+    s->lg[d] = ilog2(grid->n[d]);
+    s->total *= (int64_t)grid->n[d];
+    s->gd.lg[d] = s->lg[d];
+    s->gd.lo[d] = d < grid->ndim ? grid->lo[d] : 0.0;
+    s->gd.dx[d] = d < grid->ndim ? spacing(*grid, d) : 0.0;
+  }
+  s->gd.ndim = grid->ndim;
+  for (int d = 0; d < 3; ++d) {
+    s->pd.w[wp::CO_A + d] = to_dev(pot->a[d]);
+    s->pd.w[wp::CO_B + d] = to_dev(pot->b[d]);
+  }
+  s->pd.w[wp::CO_C] = to_dev(pot->c);
+  s->pd.w[wp::CO_S] = to_dev(pot->s);
+  s->pd.v0_kind = pot->v0_kind;
+  for (int i = 0; i < 4; ++i) s->pd.v0_par[i] = pot->v0_par[i];
+
+  // Kinetic factors exp(-i hbar k^2 tau/2m) per axis, the 1/N of the inverse
+  // transform folded into the last used axis; k^2 per axis for the energy.
+  std::vector<cx<double>> kf, kh;
+  std::vector<double> k2;
+  const double invN = 1.0 / (double)s->total;
+  for (int d = 0; d < 3; ++d) {
+    for (uint64_t m = 0; m < grid->n[d]; ++m) {
+      const double k = d < grid->ndim ? wavenumber(*grid, d, m) : 0.0;
+      const double ksq = k * k;
+      const double scale = (d == grid->ndim - 1) ? invN : 1.0;
+      const double thf = grid->hbar * ksq * grid->dt / (2.0 * grid->mass);
+      const double thh = grid->hbar * ksq * (0.5 * grid->dt) / (2.0 * grid->mass);
+      kf.push_back({scale * std::cos(thf), -scale * std::sin(thf)});
+      kh.push_back({scale * std::cos(thh), -scale * std::sin(thh)});
+      k2.push_back(ksq);
+    }
+  }
+  e = upload(&s->d_kfull, kf);
+  if (e == hipSuccess) e = upload(&s->d_khalf, kh);
+  if (e == hipSuccess) e = upload(&s->d_k2, k2);
+  // Twiddles exp(-2 pi i e/n) per axis.
+  for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+    const uint64_t n = grid->n[d];
+    std::vector<cx<double>> tw(n);
+    for (uint64_t j = 0; j < n; ++j) {
+      const double ang = 2.0 * kPi * (double)j / (double)n;
+      tw[j] = {std::cos(ang), -std::sin(ang)};
+    }
+    e = upload(&s->d_tw[d], tw);
+  }
+  if (e == hipSuccess) {
+    int64_t b = (s->total + wp::kObsThreads - 1) / wp::kObsThreads;
+    s->obs_blocks = (int)(b > 1024 ? 1024 : b);
+    e = hipMalloc((void **)&s->d_partials, sizeof(double) * 8 * (size_t)s->obs_blocks);
+  }
+  if (e == hipSuccess) e = hipMalloc((void **)&s->d_out8, sizeof(double) * 8);
+  if (e == hipSuccess) wp_state_bytes(grid, &s->psi_bytes);
+  if (e != hipSuccess) {
+    release(s);
+    delete s;
+    return e == hipErrorOutOfMemory ? WP_ENOMEM : WP_EDEVICE;
+  }
+  *out = s;
+  return WP_OK;
+}
+
+wp_status wp_destroy(wp_sim *sim) {
+  if (!sim) return WP_EINVAL;
+  (void)hipSetDevice(sim->device);
+  (void)hipStreamSynchronize(sim->stream);
+  release(sim);
+  delete sim;
+  return WP_OK;
+}
+
+wp_status wp_bind_state(wp_sim *s, void *dev_psi, uint64_t bytes) {
+  if (!s) return WP_EINVAL;
+  if (!dev_psi) return fail(s, WP_EINVAL, "bind_state: NULL pointer");
+  if (bytes < s->psi_bytes) return fail(s, WP_EINVAL, "bind_state: buffer smaller than the state");
+  if (((uintptr_t)dev_psi & 15) != 0) return fail(s, WP_EINVAL, "bind_state: buffer not 16-byte aligned");
+  (void)hipSetDevice(s->device);
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "bind_state");
+  if (s->psi_owned && s->psi) (void)hipFree(s->psi);
+  s->psi = dev_psi;
+  s->psi_owned = false;
+  s->err.clear();
+  return WP_OK;
+}
+
+void *wp_state_ptr(wp_sim *s) { return s ? s->psi : nullptr; }
+
+wp_status wp_set_state(wp_sim *s, const double *host, double t0) {
+  if (!s) return WP_EINVAL;
+  if (!host) return fail(s, WP_EINVAL, "set_state: NULL host buffer");
+  if (!std::isfinite(t0)) return fail(s, WP_EINVAL, "set_state: t0 must be finite");
+  (void)hipSetDevice(s->device);
+  hipError_t e = ensure_state(s);
+  if (e != hipSuccess) return state_fail(s, e, "set_state");
+  if (s->prec == WP_C128) {
+    e = hipMemcpyAsync(s->psi, host, s->psi_bytes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  } else {
+    std::vector<float> tmp;
+    try {
+      tmp.resize(2 * (size_t)s->total);
+    } catch (...) {
+      return fail(s, WP_ENOMEM, "set_state: host allocation failed");
+    }
+    for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)host[i];
+    e = hipMemcpyAsync(s->psi, tmp.data(), s->psi_bytes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "set_state");
+  s->t0 = t0;
+  s->step = 0;
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_set_state_gaussian(wp_sim *s, const double center[3], const double sigma[3], const double k[3],
+                                double t0) {
+  if (!s) return WP_EINVAL;
+  if (!center || !sigma || !k) return fail(s, WP_EINVAL, "set_state_gaussian: NULL array");
+  if (!std::isfinite(t0)) return fail(s, WP_EINVAL, "set_state_gaussian: t0 must be finite");
+  for (int d = 0; d < s->g.ndim; ++d)
+    if (!(sigma[d] > 0) || !std::isfinite(sigma[d]) || !std::isfinite(center[d]) || !std::isfinite(k[d]))
+      return fail(s, WP_EINVAL, "set_state_gaussian: sigma must be > 0 and all values finite");
+  (void)hipSetDevice(s->device);
+  // The Gaussian is a product over axes, so its discrete norm is the product
+  // of the per-axis norms: each axis factor is normalised on its own.
+  std::vector<cx<double>> f[3];
+  for (int d = 0; d < 3; ++d) {
+    const uint64_t n = s->g.n[d];
+    f[d].resize(n);
+    if (d >= s->g.ndim) {
+      f[d][0] = {1.0, 0.0};
+      continue;
+    }
+    const double dx = spacing(s->g, d);
+    double nrm = 0.0;
+    for (uint64_t i = 0; i < n; ++i) {
+      const double u = (s->g.lo[d] + (double)i * dx) - center[d];
+      const double amp = std::pow(2.0 / kPi, 0.25) / std::sqrt(sigma[d]) * std::exp(-u * u / (sigma[d] * sigma[d]));
+      f[d][i] = {amp * std::cos(k[d] * u), amp * std::sin(k[d] * u)};
+      nrm += (f[d][i].x * f[d][i].x + f[d][i].y * f[d][i].y) * dx;
+    }
+    const double sc = 1.0 / std::sqrt(nrm);
+    for (auto &v : f[d]) v = {v.x * sc, v.y * sc};
+  }
+  hipError_t e = ensure_state(s);
+  if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
+  cx<double> *d[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = upload(&d[i], f[i]);
+  if (e == hipSuccess) e = wp::launch_gaussian(s->prec, s->psi, s->gd, d[0], d[1], d[2], s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  for (auto p : d)
+    if (p) (void)hipFree(p);
+  if (e != hipSuccess) return hip_fail(s, e, "set_state_gaussian");
+  s->t0 = t0;
+  s->step = 0;
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_set_order(wp_sim *s, int32_t order) {
+  if (!s) return WP_EINVAL;
+  if (order != WP_ORDER_VKV && order != WP_ORDER_KVK) return fail(s, WP_EINVAL, "unknown order");
+  s->order = order;
+  return WP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Walk the launch sequence of `nsteps` steps, calling launch(kind, fn) for
+// each kernel, where fn() enqueues it.  Kinds are the WP_PASS_* values.
+template <class Launch>
+hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
+  const double tau_half = 0.5 * s->g.dt / s->g.hbar;
+  const double tau_full = s->g.dt / s->g.hbar;
+  const int prec = s->prec;
+  hipStream_t st = s->stream;
+  auto pass = [&](int kind, const wp::PassArgs &a) {
+    return launch(kind, [&]() { return wp::launch_pass(prec, a, st); });
+  };
+  if (s->g.ndim == 1) {
+    wp::Solve1DArgs a{};
+    a.psi = s->psi;
+    a.g = s->gd;
+    a.nsteps = (int64_t)nsteps;
+    a.time.t0 = s->t0;
+    a.time.dt = s->g.dt;
+    a.time.step = (int64_t)s->step;
+    a.time.step_dev = nullptr;
+    a.time.half = 0.0;
+    a.vtau_half = tau_half;
+    a.vtau_full = tau_full;
+    a.order = s->order;
+    a.pot = s->pd;
+    a.kfull = s->d_kfull;
+    a.khalf = s->d_khalf;
+    a.tw = s->d_tw[0];
+    return launch(WP_PASS_SOLVE1D, [&]() { return wp::launch_solve1d(prec, a, st); });
+  }
+  const int last = s->g.ndim - 1;
+  // Middle of a step (all axes but the first): forward over axes 1..last-1,
+  // forward + kinetic + inverse along the last axis, inverse back.
+  auto middle = [&](bool half_k) -> hipError_t {
+    hipError_t r = hipSuccess;
+    for (int d = 1; d < last && r == hipSuccess; ++d) r = pass(WP_PASS_MID_FWD, pass_args(s, d, wp::OP_FWD));
+    if (r != hipSuccess) return r;
+    wp::PassArgs k = pass_args(s, last, wp::OP_FWD | wp::OP_K | wp::OP_POST_INV);
+    if (half_k) use_half_kinetic(s, k);
+    r = pass(WP_PASS_LAST, k);
+    for (int d = last - 1; d >= 1 && r == hipSuccess; --d) r = pass(WP_PASS_MID_INV, pass_args(s, d, wp::OP_PRE_INV));
+    return r;
+  };
+  hipError_t e = hipSuccess;
+  if (s->order == WP_ORDER_VKV) {
+    // [V/2(t_n) F_0] ([middle] [F_0^-1 V(t_n+1) F_0])* ... [F_0^-1 V/2(t_N)]:
+    // equal-time potential halves of consecutive steps are merged.
+    wp::PassArgs a0 = pass_args(s, 0, wp::OP_V | wp::OP_FWD);
+    a0.time.step = (int64_t)s->step;
+    a0.vtau = tau_half;
+    e = pass(WP_PASS_EDGE, a0);
+    for (uint64_t j = 0; j < nsteps && e == hipSuccess; ++j) {
+      e = middle(false);
+      if (e != hipSuccess) break;
+      const bool lastj = (j + 1 == nsteps);
+      wp::PassArgs a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | (lastj ? 0u : wp::OP_FWD));
+      a.time.step = (int64_t)(s->step + j + 1);
+      a.vtau = lastj ? tau_half : tau_full;
+      e = pass(lastj ? WP_PASS_EDGE : WP_PASS_AXIS0, a);
+    }
+  } else {
+    // K/2 V(t_n + dt/2) K/2 with consecutive kinetic halves merged.
+    e = pass(WP_PASS_EDGE, pass_args(s, 0, wp::OP_FWD));
+    if (e == hipSuccess) e = middle(true);
+    for (uint64_t j = 0; j < nsteps && e == hipSuccess; ++j) {
+      wp::PassArgs a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | wp::OP_FWD);
+      a.time.step = (int64_t)(s->step + j);
+      a.time.half = 0.5;
+      a.vtau = tau_full;
+      e = pass(WP_PASS_AXIS0, a);
+      if (e == hipSuccess) e = middle(j + 1 == nsteps);
+    }
+    if (e == hipSuccess) e = pass(WP_PASS_EDGE, pass_args(s, 0, wp::OP_PRE_INV));
+  }
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+wp_status wp_propagate(wp_sim *s, uint64_t nsteps) {
+  if (!s) return WP_EINVAL;
+  if (nsteps == 0) return WP_OK;
+  if (nsteps > (uint64_t)1 << 40) return fail(s, WP_EINVAL, "propagate: nsteps too large");
+  (void)hipSetDevice(s->device);
+  if (hipError_t e0 = ensure_state(s); e0 != hipSuccess) return state_fail(s, e0, "propagate");
+  hipError_t e = run_schedule(s, nsteps, [](int, auto &&fn) { return fn(); });
+  if (e != hipSuccess) return hip_fail(s, e, "propagate");
+  s->step += nsteps;
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_profile_propagate(wp_sim *s, uint64_t nsteps, double *ms, uint64_t *count) {
+  if (!s) return WP_EINVAL;
+  if (!ms || !count) return fail(s, WP_EINVAL, "profile_propagate: NULL output");
+  if (nsteps == 0 || nsteps > 100000) return fail(s, WP_EINVAL, "profile_propagate: nsteps must be in 1..100000");
+  (void)hipSetDevice(s->device);
+  if (hipError_t e0 = ensure_state(s); e0 != hipSuccess) return state_fail(s, e0, "profile_propagate");
+  for (int k = 0; k < WP_PASS_KINDS; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  // One event pair per launch; durations are read after the whole sequence
+  // so that the host never waits between launches.
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  hipError_t e = run_schedule(s, nsteps, [&](int kind, auto &&fn) {
+    hipEvent_t a, b;
+    hipError_t r = hipEventCreate(&a);
+    if (r != hipSuccess) return r;
+    r = hipEventCreate(&b);
+    if (r != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return r;
+    }
+    ev.push_back({kind, {a, b}});
+    r = hipEventRecord(a, s->stream);
+    if (r == hipSuccess) r = fn();
+    if (r == hipSuccess) r = hipEventRecord(b, s->stream);
+    return r;
+  });
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  for (auto &x : ev) {
+    float m = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&m, x.second.first, x.second.second);
+    if (e == hipSuccess) {
+      ms[x.first] += m;
+      count[x.first] += 1;
+    }
+    (void)hipEventDestroy(x.second.first);
+    (void)hipEventDestroy(x.second.second);
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "profile_propagate");
+  s->step += nsteps;
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_get_state(wp_sim *s, void *host_out, int32_t as_prec) {
+  if (!s) return WP_EINVAL;
+  if (!host_out) return fail(s, WP_EINVAL, "get_state: NULL host buffer");
+  if (as_prec != WP_C64 && as_prec != WP_C128) return fail(s, WP_EINVAL, "get_state: bad precision");
+  (void)hipSetDevice(s->device);
+  hipError_t e = ensure_state(s);
+  if (e != hipSuccess) return state_fail(s, e, "get_state");
+  if (as_prec == s->prec) {
+    e = hipMemcpyAsync(host_out, s->psi, s->psi_bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  } else if (s->prec == WP_C64) {
+    std::vector<float> tmp(2 * (size_t)s->total);
+    e = hipMemcpyAsync(tmp.data(), s->psi, s->psi_bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    double *o = (double *)host_out;
+    if (e == hipSuccess)
+      for (size_t i = 0; i < tmp.size(); ++i) o[i] = tmp[i];
+  } else {
+    std::vector<double> tmp(2 * (size_t)s->total);
+    e = hipMemcpyAsync(tmp.data(), s->psi, s->psi_bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    float *o = (float *)host_out;
+    if (e == hipSuccess)
+      for (size_t i = 0; i < tmp.size(); ++i) o[i] = (float)tmp[i];
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "get_state");
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
+  if (!s) return WP_EINVAL;
+  if (!out) return fail(s, WP_EINVAL, "observables: NULL output");
+  (void)hipSetDevice(s->device);
+  if (hipError_t e0 = ensure_state(s); e0 != hipSuccess) return state_fail(s, e0, "observables");
+  const double t = s->t0 + (double)s->step * s->g.dt;
+  double dV = 1.0;
+  for (int d = 0; d < s->g.ndim; ++d) dV *= spacing(s->g, d);
+  const bool energy = (mask & WP_OBS_ENERGY) != 0;
+  wp::ObsArgs a{};
+  a.psi = s->psi;
+  a.g = s->gd;
+  a.total = s->total;
+  a.with_v = energy ? 1 : 0;
+  a.kinetic = 0;
+  a.t = t;
+  a.pot = s->pd;
+  a.partials = s->d_partials;
+  double sums[8], ksum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hipError_t e = wp::launch_observables(s->prec, a, s->obs_blocks, s->d_out8, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(sums, s->d_out8, sizeof(sums), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess && energy) {
+    if (!s->scratch) e = hipMalloc(&s->scratch, s->psi_bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
+    for (int d = 0; d < s->g.ndim && e == hipSuccess; ++d) {
+      wp::PassArgs p = pass_args(s, d, wp::OP_FWD);
+      p.psi = s->scratch;
+      if (s->g.ndim == 1) {
+        if (!wp::pass_supported(s->prec, s->lg[0])) {
+          e = hipErrorNotSupported;
+          break;
+        }
+      }
+      e = wp::launch_pass(s->prec, p, s->stream);
+    }
+    if (e == hipSuccess) {
+      wp::ObsArgs k = a;
+      k.psi = s->scratch;
+      k.kinetic = 1;
+      k.with_v = 0;
+      int off = 0;
+      for (int d = 0; d < 3; ++d) {
+        k.k2tab[d] = s->d_k2 + off;
+        off += (int)s->g.n[d];
+      }
+      e = wp::launch_observables(s->prec, k, s->obs_blocks, s->d_out8, s->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(ksum, s->d_out8, sizeof(ksum), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  }
+  if (e == hipErrorNotSupported) return fail(s, WP_EUNSUPPORTED, "observables: energy needs an axis <= 4096 points");
+  if (e != hipSuccess) return hip_fail(s, e, "observables");
+  double all[8];
+  all[0] = std::sqrt(sums[0] * dV);
+  for (int d = 0; d < 3; ++d) {
+    all[1 + d] = d < s->g.ndim ? sums[1 + d] * dV : 0.0;
+    all[4 + d] = d < s->g.ndim ? sums[4 + d] * dV : 0.0;
+  }
+  all[7] = energy ? (s->g.hbar * s->g.hbar / (2.0 * s->g.mass)) * ksum[0] * dV / (double)s->total + sums[7] * dV
+                  : 0.0;
+  for (int i = 0; i < 8; ++i) out[i] = (mask & (1u << i)) ? all[i] : 0.0;
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_get_time(wp_sim *s, double *t, uint64_t *step) {
+  if (!s) return WP_EINVAL;
+  if (t) *t = s->t0 + (double)s->step * s->g.dt;
+  if (step) *step = s->step;
+  return WP_OK;
+}
+
+wp_status wp_synchronize(wp_sim *s) {
+  if (!s) return WP_EINVAL;
+  (void)hipSetDevice(s->device);
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "synchronize");
+  return WP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// wp_device.hpp -- device building blocks of the split-operator step on gfx950:
+// complex arithmetic with FP64-accurate factor multiplies, the time-dependent
+// potential family, and the LDS-staged line FFT.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wp {
+
+// ---------------------------------------------------------------------------
+// complex values
+// ---------------------------------------------------------------------------
+template <class R>
+struct cx {
+  R x, y;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+
+// Product of two FP64 factors.
+__device__ __forceinline__ cx<double> cmul(cx<double> a, cx<double> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// Multiply a value by an FP64 factor and round the result once into the
+// value's precision.  Rounding a phase or twiddle factor to FP32 first would
+// bias |psi| by the same relative amount at every step; here the only
+// rounding is that of the product.
+__device__ __forceinline__ cx<double> mul_acc(cx<double> a, cx<double> w) { return cmul(a, w); }
+__device__ __forceinline__ cx<float> mul_acc(cx<float> a, cx<double> w) {
+  double ax = a.x, ay = a.y;
+  return {(float)(ax * w.x - ay * w.y), (float)(ax * w.y + ay * w.x)};
+}
+
+// Multiply by -i (forward transform) or +i (inverse transform).
+template <bool INV, class R>
+__device__ __forceinline__ cx<R> mul_mi(cx<R> a) {
+  return INV ? cx<R>{-a.y, a.x} : cx<R>{a.y, -a.x};
+}
+
+// s * sqrt(1/2) with one rounding: in FP32 the constant is carried as a
+// two-term sum so that no rounded constant is applied at every transform.
+__device__ __forceinline__ double mul_rsqrt2(double s) { return s * 0.70710678118654752440; }
+__device__ __forceinline__ float mul_rsqrt2(float s) {
+  constexpr float hi = 0.70710678118654752440f;
+  constexpr float lo = (float)(0.70710678118654752440 - (double)hi);
+  return fmaf(s, hi, s * lo);
+}
+
+// Multiply by exp(-+ 2 pi i/8) and exp(-+ 6 pi i/8) (the radix-8 inner
+// twiddles; upper sign forward).
+template <bool INV, class R>
+__device__ __forceinline__ cx<R> mul_w8_1(cx<R> a) {
+  // forward: (1 - i)/sqrt2 ; inverse: (1 + i)/sqrt2
+  return INV ? cx<R>{mul_rsqrt2(a.x - a.y), mul_rsqrt2(a.x + a.y)}
+             : cx<R>{mul_rsqrt2(a.x + a.y), mul_rsqrt2(a.y - a.x)};
+}
+template <bool INV, class R>
+__device__ __forceinline__ cx<R> mul_w8_3(cx<R> a) {
+  // forward: (-1 - i)/sqrt2 ; inverse: (-1 + i)/sqrt2
+  return INV ? cx<R>{mul_rsqrt2(-a.x - a.y), mul_rsqrt2(a.x - a.y)}
+             : cx<R>{mul_rsqrt2(a.y - a.x), mul_rsqrt2(-a.x - a.y)};
+}
+
+// Small DFTs in registers (unnormalised; INV selects exp(+2 pi i jm/n)).
+template <bool INV, class R>
+__device__ __forceinline__ void dft2(cx<R> &a, cx<R> &b) {
+  cx<R> s = cadd(a, b), d = csub(a, b);
+  a = s;
+  b = d;
+}
+
+template <bool INV, class R>
+__device__ __forceinline__ void dft4(cx<R> &u0, cx<R> &u1, cx<R> &u2, cx<R> &u3) {
+  cx<R> s0 = cadd(u0, u2), s1 = csub(u0, u2);
+  cx<R> s2 = cadd(u1, u3), s3 = mul_mi<INV>(csub(u1, u3));
+  u0 = cadd(s0, s2);
+  u1 = cadd(s1, s3);
+  u2 = csub(s0, s2);
+  u3 = csub(s1, s3);
+}
+
+// 8-point DFT as 2 x 4: radix-2 between r and r+4, inner twiddles W8^r on
+// the difference terms, then two 4-point DFTs giving the even and odd outputs.
+template <bool INV, class R>
+__device__ __forceinline__ void dft8(cx<R> *v) {
+  cx<R> a0 = cadd(v[0], v[4]), b0 = csub(v[0], v[4]);
+  cx<R> a1 = cadd(v[1], v[5]), b1 = csub(v[1], v[5]);
+  cx<R> a2 = cadd(v[2], v[6]), b2 = csub(v[2], v[6]);
+  cx<R> a3 = cadd(v[3], v[7]), b3 = csub(v[3], v[7]);
+  b1 = mul_w8_1<INV>(b1);
+  b2 = mul_mi<INV>(b2);
+  b3 = mul_w8_3<INV>(b3);
+  dft4<INV>(a0, a1, a2, a3);
+  dft4<INV>(b0, b1, b2, b3);
+  v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+  v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
+}
+
+template <int RAD, bool INV, class R>
+__device__ __forceinline__ void dft(cx<R> *x) {
+  if constexpr (RAD == 2) dft2<INV>(x[0], x[1]);
+  else if constexpr (RAD == 4) dft4<INV>(x[0], x[1], x[2], x[3]);
+  else dft8<INV>(x);
+}
+
+// ---------------------------------------------------------------------------
+// line FFT: N = 2^p points of one line held by L = N/VPT threads, VPT values
+// each.  Thread t holds element t + L*u in slot u ("stride-L layout") on entry
+// and on exit, in natural order, for both directions.
+//
+// Stages follow the Stockham autosort formulation (Stockham 1966; as used for
+// GPUs by Govindaraju et al., SC 2008): with Ls the product of the radices
+// done so far, butterfly j takes inputs j + r N/R, multiplies input r by
+// exp(-+2 pi i r (j mod Ls)/(Ls R)), does an R-point DFT and writes output q
+// to (j - j mod Ls) R + (j mod Ls) + q Ls.  The first stage takes its inputs
+// straight from registers and the last leaves its outputs in registers, so a
+// transform of 8^s points exchanges through LDS s-1 times.  The first stage
+// has radix 2, 4 or 8 so that the rest are radix 8.
+//
+// `Lds` maps an element index of this thread's line to an LDS reference.
+// Twiddles: tw[e] = exp(-2 pi i e / N) in FP64, e < N.
+// ---------------------------------------------------------------------------
+template <int N>
+struct fft_shape {
+  static constexpr int lg = __builtin_ctz(N);
+  static constexpr int VPT = N < 8 ? N : 8;
+  static constexpr int L = N / VPT;
+  static constexpr int R0 = (N <= 8) ? N : ((lg % 3 == 0) ? 8 : (1 << (lg % 3)));
+};
+
+template <int N, int RAD, int LS, bool INV, class R, class Lds>
+__device__ __forceinline__ void fft_stage(cx<R> (&v)[fft_shape<N>::VPT], int t,
+                                          const cx<double> *tw, Lds lds) {
+  constexpr int VPT = fft_shape<N>::VPT;
+  constexpr int L = fft_shape<N>::L;
+  constexpr int M = VPT / RAD;  // butterflies per thread
+  constexpr bool LAST = (LS * RAD == N);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int j = t + m * L;
+    const int k = j & (LS - 1);
+    cx<R> x[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) x[r] = v[m + r * M];
+    if constexpr (LS > 1) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        cx<double> w = tw[(r * k) * (N / (LS * RAD))];
+        if (INV) w.y = -w.y;
+        x[r] = mul_acc(x[r], w);
+      }
+    }
+    dft<RAD, INV>(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) v[m + q * M] = x[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) lds((j - k) * RAD + k + q * LS) = x[q];
+    }
+  }
+}
+
+template <int N, int RAD, int LS, bool INV, class R, class Lds>
+__device__ __forceinline__ void fft_stages(cx<R> (&v)[fft_shape<N>::VPT], int t,
+                                           const cx<double> *tw, Lds lds) {
+  constexpr int L = fft_shape<N>::L;
+  constexpr int VPT = fft_shape<N>::VPT;
+  fft_stage<N, RAD, LS, INV>(v, t, tw, lds);
+  if constexpr (LS * RAD < N) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = lds(t + L * u);
+    // The next stage writes LDS only if it is not the last one.
+    if constexpr (LS * RAD * 8 < N) __syncthreads();
+    fft_stages<N, 8, LS * RAD, INV>(v, t, tw, lds);
+  }
+}
+
+// Whole line transform.  Every thread of the workgroup must call it (it
+// contains barriers) whether or not its line is valid.  It starts with a
+// barrier so that earlier LDS reads of the same buffer are complete.
+template <int N, bool INV, class R, class Lds>
+__device__ __forceinline__ void line_fft(cx<R> (&v)[fft_shape<N>::VPT], int t,
+                                         const cx<double> *tw, Lds lds) {
+  if constexpr (N > 8) __syncthreads();
+  fft_stages<N, fft_shape<N>::R0, 1, INV>(v, t, tw, lds);
+}
+
+// ---------------------------------------------------------------------------
+// time-dependent potential
+// ---------------------------------------------------------------------------
+struct WaveDev {
+  int32_t kind;
+  double A0, A1, omega, phase, tc, tau, ti, tf;
+};
+
+// Coefficient slots: a0 a1 a2 b0 b1 b2 c s.
+enum { CO_A = 0, CO_B = 3, CO_C = 6, CO_S = 7, CO_COUNT = 8 };
+
+struct PotDev {
+  WaveDev w[CO_COUNT];
+  int32_t v0_kind;  // 0 none, 1 soft-core, 2 Morse
+  double v0_par[4];
+};
+
+__device__ __forceinline__ double wave_value(const WaveDev &w, double t) {
+  switch (w.kind) {
+    case 0: return w.A0;
+    case 1: return w.A0 + w.A1 * sin(w.omega * t + w.phase);
+    case 2: return w.A0 + w.A1 * cos(w.omega * t + w.phase);
+    case 3: {
+      double u = (t - w.tc) / w.tau;
+      return w.A0 + w.A1 * exp(-u * u) * cos(w.omega * t + w.phase);
+    }
+    case 4: {
+      if (t < w.ti || t > w.tf) return w.A0;
+      double e = sin(M_PI * (t - w.ti) / (w.tf - w.ti));
+      return w.A0 + w.A1 * e * e * cos(w.omega * t + w.phase);
+    }
+    default: return 0.0;
+  }
+}
+
+// Non-separable part V0(x) of the potential.
+__device__ __forceinline__ double v0_value(const PotDev &p, double x0, double x1, double x2, int ndim) {
+  if (p.v0_kind == 1) {
+    double r2 = x0 * x0;
+    if (ndim > 1) r2 += x1 * x1;
+    if (ndim > 2) r2 += x2 * x2;
+    return -p.v0_par[0] / sqrt(r2 + p.v0_par[1]);
+  }
+  if (p.v0_kind == 2) {
+    double e = 1.0 - exp(-p.v0_par[1] * (x0 - p.v0_par[2]));
+    return p.v0_par[0] * e * e;
+  }
+  return 0.0;
+}
+
+// exp(-i theta) in FP64.
+__device__ __forceinline__ cx<double> expmi(double th) {
+  double s, c;
+  sincos(th, &s, &c);
+  return {c, -s};
+}
+
+// ---------------------------------------------------------------------------
+// storage conversions
+// ---------------------------------------------------------------------------
+template <class R>
+struct storage;
+template <>
+struct storage<double> {
+  using type = double2;
+};
+template <>
+struct storage<float> {
+  using type = float2;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> load_cx(const typename storage<R>::type *p) {
+  typename storage<R>::type v = *p;
+  return {v.x, v.y};
+}
+template <class R>
+__device__ __forceinline__ void store_cx(typename storage<R>::type *p, cx<R> v) {
+  typename storage<R>::type s;
+  s.x = v.x;
+  s.y = v.y;
+  *p = s;
+}
+
+}  // namespace wp

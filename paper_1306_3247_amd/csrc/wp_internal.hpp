@@ -1,0 +1,97 @@
+// wp_internal.hpp -- kernel argument blocks and launcher entry points shared
+// by the kernel translation unit and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wp_device.hpp"
+
+namespace wp {
+
+// Operations of one line pass, applied in this order.
+enum : uint32_t {
+  OP_PRE_INV = 1u << 0,   // inverse line FFT (unnormalised)
+  OP_V = 1u << 1,         // multiply by exp(-i V(x,t) vtau)
+  OP_FWD = 1u << 2,       // forward line FFT
+  OP_K = 1u << 3,         // multiply by the kinetic factor (1/N folded in)
+  OP_POST_INV = 1u << 4,  // inverse line FFT
+};
+
+struct GridDev {
+  int32_t ndim;
+  int32_t lg[3];  // log2 of the axis lengths (0 on unused axes)
+  double lo[3], dx[3];
+};
+
+// Time of a potential evaluation: t = t0 + (step + (step_dev ? *step_dev : 0)) * dt
+// (time by multiplication, never by accumulation).
+struct TimeDev {
+  double t0, dt;
+  int64_t step;
+  const int64_t *step_dev;
+  double half;  // 0.5 to sample at the step midpoint, else 0
+};
+
+__device__ __forceinline__ double time_of(const TimeDev &T) {
+  int64_t n = T.step + (T.step_dev ? *T.step_dev : 0);
+  return T.t0 + ((double)n + T.half) * T.dt;
+}
+
+struct PassArgs {
+  void *psi;
+  GridDev g;
+  int32_t axis;      // line axis
+  int32_t lg_inner;  // log2 of the product of the axis lengths after `axis`
+  int64_t n_lines;
+  uint32_t ops;
+  TimeDev time;      // when OP_V
+  double vtau;       // phase = V * vtau (dt/2hbar or dt/hbar)
+  PotDev pot;
+  const cx<double> *ktab[3];  // kinetic factors per axis (OP_K)
+  const cx<double> *tw;       // twiddles exp(-2 pi i e/N), e < N
+};
+
+struct Solve1DArgs {
+  void *psi;
+  GridDev g;
+  int64_t nsteps;
+  TimeDev time;       // step = index of the first step
+  double vtau_half;   // dt/2hbar
+  double vtau_full;   // dt/hbar
+  int32_t order;      // 0: V-K-V, 1: K-V-K
+  PotDev pot;
+  const cx<double> *kfull;  // exp(-i hbar k^2 dt/2m)/N
+  const cx<double> *khalf;  // exp(-i hbar k^2 dt/4m)/N (K-V-K order)
+  const cx<double> *tw;
+};
+
+struct ObsArgs {
+  const void *psi;
+  GridDev g;
+  int64_t total;
+  int32_t with_v;     // accumulate V|psi|^2
+  int32_t kinetic;    // psi is in momentum space: accumulate k^2 |psi|^2
+  double t;
+  PotDev pot;
+  const double *k2tab[3];  // k^2 per axis (kinetic)
+  double *partials;        // [blocks][8]
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s);
+hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s);
+hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<double> *f0,
+                           const cx<double> *f1, const cx<double> *f2, hipStream_t s);
+hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src, int64_t count,
+                          hipStream_t s);
+hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s);
+
+// Largest line length (points) supported by the line-pass kernels and by the
+// single-workgroup 1D solver.
+constexpr int kMaxLinePass = 4096;
+constexpr int kMaxLine1D = 8192;
+constexpr int kObsThreads = 256;
+
+bool pass_supported(int prec, int lgN);
+
+}  // namespace wp

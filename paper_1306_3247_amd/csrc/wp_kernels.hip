@@ -1,0 +1,480 @@
+// wp_kernels.hip -- HIP kernels of the split-operator step for gfx950.
+//
+// Data layout: psi is row-major [n0][n1][n2], interleaved complex, FP32 or
+// FP64.  A multi-dimensional step is a sequence of line passes.  Each pass
+// reads every line along one axis from HBM once, does all of its work in
+// registers and LDS (inverse FFT, potential phase, forward FFT, kinetic
+// phase, ...) and writes the line back once.
+#include "wp_internal.hpp"
+
+namespace wp {
+
+// ---------------------------------------------------------------------------
+// workgroup shape of a line pass
+// ---------------------------------------------------------------------------
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+constexpr int imin(int a, int b) { return a < b ? a : b; }
+constexpr int imax(int a, int b) { return a > b ? a : b; }
+
+template <class R, int N, bool STRIDED>
+struct pass_cfg {
+  static constexpr int L = fft_shape<N>::L;
+  static constexpr int VPT = fft_shape<N>::VPT;
+  static constexpr int ELEM = (int)sizeof(cx<R>);
+  // One padding element after every 8 keeps the Stockham scatter of the
+  // first stage (stride 8 elements) off a single bank group.
+  static constexpr int NP = N + N / 8;
+  // Twiddles live in LDS up to 1024 points; longer lines read them from the
+  // (cached) global table so that the line data still fits.
+  static constexpr bool TW_LDS = N <= 1024;
+  // Lines per workgroup: about 32 KiB of line data, at least enough
+  // neighbouring lines (strided axes) that every row segment read is a full
+  // 128-byte cache line, at most 1024 threads and 96 KiB of line data.
+  static constexpr int T_MEM = imax(1, (32768 / ELEM) / N);
+  static constexpr int T_THR = 1024 / L;
+  static constexpr int T_LDS = imax(1, pow2_floor(98304 / (NP * ELEM)));
+  static constexpr int T_MIN = STRIDED ? 128 / ELEM : 1;
+  static constexpr int TILE = imin(imin(imax(T_MEM, T_MIN), T_THR), T_LDS);
+  static constexpr int THREADS = TILE * L;
+  static constexpr int LDS_ELEMS = (N > 8) ? TILE * NP : 1;
+};
+
+__device__ __forceinline__ void decode_line(const GridDev &g, int axis, int64_t o, int64_t c,
+                                            int idx[3]) {
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    if (d > axis) {
+      idx[d] = (int)(c & ((1 << g.lg[d]) - 1));
+      c >>= g.lg[d];
+    }
+  }
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    if (d < axis) {
+      idx[d] = (int)(o & ((1 << g.lg[d]) - 1));
+      o >>= g.lg[d];
+    }
+  }
+  idx[axis] = 0;
+}
+
+__device__ __forceinline__ double coord(const GridDev &g, int d, int i) {
+  return g.lo[d] + (double)i * g.dx[d];
+}
+
+// ---------------------------------------------------------------------------
+// line pass
+// ---------------------------------------------------------------------------
+template <class R, int N, bool STRIDED>
+__global__ void __launch_bounds__((pass_cfg<R, N, STRIDED>::THREADS)) pass_kernel(PassArgs a) {
+  using C = pass_cfg<R, N, STRIDED>;
+  using S = typename storage<R>::type;
+  constexpr int L = C::L, VPT = C::VPT, TILE = C::TILE, NT = C::THREADS;
+
+  __shared__ cx<R> s_data[C::LDS_ELEMS];
+  __shared__ cx<double> s_tw[C::TW_LDS ? N : 1];
+  __shared__ cx<double> s_tab[N];
+  __shared__ cx<double> s_line[TILE];
+  __shared__ double s_coef[CO_COUNT];
+
+  const int tid = threadIdx.x;
+  const int tau = STRIDED ? tid % TILE : tid / L;
+  const int t = STRIDED ? tid / TILE : tid % L;
+  const int64_t line = (int64_t)blockIdx.x * TILE + tau;
+  const bool valid = line < a.n_lines;
+  const int lgi = a.lg_inner;
+  const int64_t o = line >> lgi, c = line & (((int64_t)1 << lgi) - 1);
+  const int64_t base = (o << (fft_shape<N>::lg + lgi)) + c;
+  S *psi = (S *)a.psi;
+  const uint32_t ops = a.ops;
+
+  cx<R> v[VPT];
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = load_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi));
+  } else {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
+  }
+
+  if constexpr (C::TW_LDS)
+    for (int e = tid; e < N; e += NT) s_tw[e] = a.tw[e];
+  const cx<double> *tw = C::TW_LDS ? (const cx<double> *)s_tw : a.tw;
+  if ((ops & OP_V) && tid < CO_COUNT) s_coef[tid] = wave_value(a.pot.w[tid], time_of(a.time));
+  if (ops & OP_K) {
+    for (int e = tid; e < N; e += NT) s_tab[e] = a.ktab[a.axis][e];
+    if (tid < TILE) {
+      const int64_t l2 = (int64_t)blockIdx.x * TILE + tid;
+      if (l2 < a.n_lines) {
+        int idx[3];
+        decode_line(a.g, a.axis, l2 >> lgi, l2 & (((int64_t)1 << lgi) - 1), idx);
+        cx<double> f = {1.0, 0.0};
+        for (int d = 0; d < a.g.ndim; ++d)
+          if (d != a.axis) f = cmul(f, a.ktab[d][idx[d]]);
+        s_line[tid] = f;
+      }
+    }
+  }
+  __syncthreads();
+  const bool separable = a.pot.v0_kind == 0;
+  if ((ops & OP_V) && separable) {
+    const int ax = a.axis;
+    const double ca = s_coef[CO_A + ax], cb = s_coef[CO_B + ax];
+    for (int e = tid; e < N; e += NT) {
+      const double x = coord(a.g, ax, e);
+      s_tab[e] = expmi(a.vtau * (ca * x + cb * x * x));
+    }
+    if (tid < TILE) {
+      const int64_t l2 = (int64_t)blockIdx.x * TILE + tid;
+      if (l2 < a.n_lines) {
+        int idx[3];
+        decode_line(a.g, ax, l2 >> lgi, l2 & (((int64_t)1 << lgi) - 1), idx);
+        double th = s_coef[CO_C];
+        for (int d = 0; d < a.g.ndim; ++d) {
+          if (d == ax) continue;
+          const double x = coord(a.g, d, idx[d]);
+          th += s_coef[CO_A + d] * x + s_coef[CO_B + d] * x * x;
+        }
+        s_line[tid] = expmi(a.vtau * th);
+      }
+    }
+    __syncthreads();
+  }
+
+  auto lds = [&](int i) -> cx<R> & {
+    if constexpr (STRIDED) return s_data[(i + (i >> 3)) * TILE + tau];
+    else return s_data[tau * C::NP + i + (i >> 3)];
+  };
+
+  if (ops & OP_PRE_INV) line_fft<N, true>(v, t, tw, lds);
+  if (ops & OP_V) {
+    if (separable) {
+      const cx<double> fl = s_line[tau];
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_tab[t + L * u], fl));
+    } else {
+      int idx[3];
+      decode_line(a.g, a.axis, o, c, idx);
+      double xs[3];
+      for (int d = 0; d < 3; ++d) xs[d] = coord(a.g, d, idx[d]);
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        xs[a.axis] = coord(a.g, a.axis, t + L * u);
+        double th = s_coef[CO_C];
+        for (int d = 0; d < a.g.ndim; ++d) th += s_coef[CO_A + d] * xs[d] + s_coef[CO_B + d] * xs[d] * xs[d];
+        th += s_coef[CO_S] * v0_value(a.pot, xs[0], xs[1], xs[2], a.g.ndim);
+        v[u] = mul_acc(v[u], expmi(a.vtau * th));
+      }
+    }
+  }
+  if (ops & OP_FWD) line_fft<N, false>(v, t, tw, lds);
+  if (ops & OP_K) {
+    const cx<double> fl = s_line[tau];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_tab[t + L * u], fl));
+  }
+  if (ops & OP_POST_INV) line_fft<N, true>(v, t, tw, lds);
+
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) store_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
+  }
+}
+
+template <class R, int N, bool STRIDED>
+static hipError_t launch_pass_t(const PassArgs &a, hipStream_t s) {
+  using C = pass_cfg<R, N, STRIDED>;
+  const int64_t blocks = (a.n_lines + C::TILE - 1) / C::TILE;
+  hipLaunchKernelGGL((pass_kernel<R, N, STRIDED>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class R, bool STRIDED>
+static hipError_t dispatch_pass(int lgN, const PassArgs &a, hipStream_t s) {
+  switch (lgN) {
+    case 1: return launch_pass_t<R, 2, STRIDED>(a, s);
+    case 2: return launch_pass_t<R, 4, STRIDED>(a, s);
+    case 3: return launch_pass_t<R, 8, STRIDED>(a, s);
+    case 4: return launch_pass_t<R, 16, STRIDED>(a, s);
+    case 5: return launch_pass_t<R, 32, STRIDED>(a, s);
+    case 6: return launch_pass_t<R, 64, STRIDED>(a, s);
+    case 7: return launch_pass_t<R, 128, STRIDED>(a, s);
+    case 8: return launch_pass_t<R, 256, STRIDED>(a, s);
+    case 9: return launch_pass_t<R, 512, STRIDED>(a, s);
+    case 10: return launch_pass_t<R, 1024, STRIDED>(a, s);
+    case 11: return launch_pass_t<R, 2048, STRIDED>(a, s);
+    case 12: return launch_pass_t<R, 4096, STRIDED>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool pass_supported(int prec, int lgN) { return (prec == 1 || prec == 2) && lgN >= 1 && lgN <= 12; }
+
+hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s) {
+  const int lgN = a.g.lg[a.axis];
+  if (!pass_supported(prec, lgN)) return hipErrorInvalidValue;
+  if ((a.ops & OP_V) && (a.ops & OP_K)) return hipErrorInvalidValue;
+  const bool strided = a.lg_inner > 0;
+  if (prec == 2) return strided ? dispatch_pass<double, true>(lgN, a, s) : dispatch_pass<double, false>(lgN, a, s);
+  return strided ? dispatch_pass<float, true>(lgN, a, s) : dispatch_pass<float, false>(lgN, a, s);
+}
+
+// ---------------------------------------------------------------------------
+// 1D solve in one workgroup: the whole line stays in registers and LDS for
+// all steps; HBM is read once and written once.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double step_time(const TimeDev &T, int64_t s, double half) {
+  int64_t n = T.step + s + (T.step_dev ? *T.step_dev : 0);
+  return T.t0 + ((double)n + half) * T.dt;
+}
+
+template <class R, int N>
+__global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a) {
+  using S = typename storage<R>::type;
+  constexpr int L = fft_shape<N>::L, VPT = fft_shape<N>::VPT;
+  constexpr int NP = N + N / 8;
+  __shared__ cx<R> s_data[N > 8 ? NP : 1];
+  __shared__ double s_coef[CO_COUNT];
+  const int t = threadIdx.x;
+  S *psi = (S *)a.psi;
+
+  cx<R> v[VPT];
+  cx<double> kf[VPT];
+  double xs[VPT];
+  const bool kvk = a.order == 1;
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    v[u] = load_cx<R>(psi + t + L * u);
+    kf[u] = kvk ? a.khalf[t + L * u] : a.kfull[t + L * u];
+    xs[u] = a.g.lo[0] + (double)(t + L * u) * a.g.dx[0];
+  }
+  auto lds = [&](int i) -> cx<R> & { return s_data[i + (i >> 3)]; };
+
+  auto apply_v = [&](double time, double vtau) {
+    __syncthreads();
+    for (int k = t; k < CO_COUNT; k += L) s_coef[k] = wave_value(a.pot.w[k], time);
+    __syncthreads();
+    const double ca = s_coef[CO_A], cb = s_coef[CO_B], cc = s_coef[CO_C], cs = s_coef[CO_S];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      double th = cc + (ca * xs[u] + cb * xs[u] * xs[u]);
+      if (a.pot.v0_kind != 0) th += cs * v0_value(a.pot, xs[u], 0.0, 0.0, 1);
+      v[u] = mul_acc(v[u], expmi(vtau * th));
+    }
+  };
+  auto apply_k = [&](bool half_factor) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      cx<double> f = kf[u];
+      if (half_factor) f = a.khalf[t + L * u];
+      v[u] = mul_acc(v[u], f);
+    }
+  };
+
+  const int64_t ns = a.nsteps;
+  if (!kvk) {
+    for (int64_t s = 0; s < ns; ++s) {
+      if (s == 0) apply_v(step_time(a.time, 0, 0.0), a.vtau_half);
+      line_fft<N, false>(v, t, a.tw, lds);
+      apply_k(false);
+      line_fft<N, true>(v, t, a.tw, lds);
+      apply_v(step_time(a.time, s + 1, 0.0), s + 1 == ns ? a.vtau_half : a.vtau_full);
+    }
+  } else if (ns > 0) {
+    // K/2 V K/2 with consecutive kinetic halves merged into full steps.
+    line_fft<N, false>(v, t, a.tw, lds);
+    apply_k(true);
+    for (int64_t s = 0; s < ns; ++s) {
+      line_fft<N, true>(v, t, a.tw, lds);
+      apply_v(step_time(a.time, s, 0.5), a.vtau_full);
+      line_fft<N, false>(v, t, a.tw, lds);
+      if (s + 1 == ns) {
+        apply_k(true);
+      } else {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], a.kfull[t + L * u]);
+      }
+    }
+    line_fft<N, true>(v, t, a.tw, lds);
+  }
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) store_cx<R>(psi + t + L * u, v[u]);
+}
+
+template <class R, int N>
+static hipError_t launch_solve1d_t(const Solve1DArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((solve1d_kernel<R, N>), dim3(1), dim3(fft_shape<N>::L), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class R>
+static hipError_t dispatch_solve1d(int lgN, const Solve1DArgs &a, hipStream_t s) {
+  switch (lgN) {
+    case 1: return launch_solve1d_t<R, 2>(a, s);
+    case 2: return launch_solve1d_t<R, 4>(a, s);
+    case 3: return launch_solve1d_t<R, 8>(a, s);
+    case 4: return launch_solve1d_t<R, 16>(a, s);
+    case 5: return launch_solve1d_t<R, 32>(a, s);
+    case 6: return launch_solve1d_t<R, 64>(a, s);
+    case 7: return launch_solve1d_t<R, 128>(a, s);
+    case 8: return launch_solve1d_t<R, 256>(a, s);
+    case 9: return launch_solve1d_t<R, 512>(a, s);
+    case 10: return launch_solve1d_t<R, 1024>(a, s);
+    case 11: return launch_solve1d_t<R, 2048>(a, s);
+    case 12: return launch_solve1d_t<R, 4096>(a, s);
+    case 13: return launch_solve1d_t<R, 8192>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s) {
+  const int lgN = a.g.lg[0];
+  return prec == 2 ? dispatch_solve1d<double>(lgN, a, s) : dispatch_solve1d<float>(lgN, a, s);
+}
+
+// ---------------------------------------------------------------------------
+// initial state, conversions
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void gaussian_kernel(void *out, GridDev g, const cx<double> *f0, const cx<double> *f1,
+                                const cx<double> *f2, int64_t total) {
+  using S = typename storage<R>::type;
+  S *psi = (S *)out;
+  const int m1 = (1 << g.lg[1]) - 1, m2 = (1 << g.lg[2]) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int i2 = (int)(i & m2), i1 = (int)((i >> g.lg[2]) & m1);
+    const int64_t i0 = i >> (g.lg[1] + g.lg[2]);
+    const cx<double> f = cmul(cmul(f0[i0], f1[i1]), f2[i2]);
+    store_cx<R>(psi + i, cx<R>{(R)f.x, (R)f.y});
+  }
+}
+
+static unsigned grid_blocks(int64_t total, int threads) {
+  int64_t b = (total + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<double> *f0,
+                           const cx<double> *f1, const cx<double> *f2, hipStream_t s) {
+  const int64_t total = (int64_t)1 << (g.lg[0] + g.lg[1] + g.lg[2]);
+  const unsigned b = grid_blocks(total, 256);
+  if (prec == 2) hipLaunchKernelGGL(gaussian_kernel<double>, dim3(b), dim3(256), 0, s, psi, g, f0, f1, f2, total);
+  else hipLaunchKernelGGL(gaussian_kernel<float>, dim3(b), dim3(256), 0, s, psi, g, f0, f1, f2, total);
+  return hipGetLastError();
+}
+
+template <class D, class Sx>
+__global__ void convert_kernel(D *dst, const Sx *src, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    Sx v = src[i];
+    D w;
+    w.x = v.x;
+    w.y = v.y;
+    dst[i] = w;
+  }
+}
+
+hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src, int64_t count,
+                          hipStream_t s) {
+  const unsigned b = grid_blocks(count, 256);
+  if (to_prec == 2 && from_prec == 1)
+    hipLaunchKernelGGL((convert_kernel<double2, float2>), dim3(b), dim3(256), 0, s, (double2 *)dst, (const float2 *)src, count);
+  else if (to_prec == 1 && from_prec == 2)
+    hipLaunchKernelGGL((convert_kernel<float2, double2>), dim3(b), dim3(256), 0, s, (float2 *)dst, (const double2 *)src, count);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// observables: deterministic FP64 reductions.  Every block sums a fixed set
+// of points (grid-stride order with a fixed grid), reduces in LDS by a fixed
+// tree, and one final block adds the block partials in index order.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void __launch_bounds__(kObsThreads) obs_kernel(ObsArgs a) {
+  using S = typename storage<R>::type;
+  __shared__ double s_red[CO_COUNT][kObsThreads];
+  __shared__ double s_coef[CO_COUNT];
+  const int tid = threadIdx.x;
+  if (a.with_v && tid < CO_COUNT) s_coef[tid] = wave_value(a.pot.w[tid], a.t);
+  __syncthreads();
+  const S *psi = (const S *)a.psi;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int m1 = (1 << a.g.lg[1]) - 1, m2 = (1 << a.g.lg[2]) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * kObsThreads + tid; i < a.total;
+       i += (int64_t)gridDim.x * kObsThreads) {
+    const S p = psi[i];
+    const double pr = p.x, pi = p.y;
+    const double w = pr * pr + pi * pi;
+    const int i2 = (int)(i & m2), i1 = (int)((i >> a.g.lg[2]) & m1);
+    const int i0 = (int)(i >> (a.g.lg[1] + a.g.lg[2]));
+    if (a.kinetic) {
+      acc[0] += (a.k2tab[0][i0] + a.k2tab[1][i1] + a.k2tab[2][i2]) * w;
+    } else {
+      const double x0 = a.g.lo[0] + (double)i0 * a.g.dx[0];
+      const double x1 = a.g.lo[1] + (double)i1 * a.g.dx[1];
+      const double x2 = a.g.lo[2] + (double)i2 * a.g.dx[2];
+      acc[0] += w;
+      acc[1] += x0 * w;
+      acc[2] += x1 * w;
+      acc[3] += x2 * w;
+      acc[4] += x0 * x0 * w;
+      acc[5] += x1 * x1 * w;
+      acc[6] += x2 * x2 * w;
+      if (a.with_v) {
+        const double xs[3] = {x0, x1, x2};
+        double v = s_coef[CO_C];
+        for (int d = 0; d < a.g.ndim; ++d) v += s_coef[CO_A + d] * xs[d] + s_coef[CO_B + d] * xs[d] * xs[d];
+        if (a.pot.v0_kind != 0) v += s_coef[CO_S] * v0_value(a.pot, x0, x1, x2, a.g.ndim);
+        acc[7] += v * w;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s_red[k][tid] = acc[k];
+  __syncthreads();
+  for (int h = kObsThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s_red[k][tid] += s_red[k][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid < 8) a.partials[(int64_t)blockIdx.x * 8 + tid] = s_red[tid][0];
+}
+
+__global__ void __launch_bounds__(kObsThreads) obs_final_kernel(const double *partials, int blocks, double *out) {
+  __shared__ double s_red[8][kObsThreads];
+  const int tid = threadIdx.x;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < blocks; b += kObsThreads)
+    for (int k = 0; k < 8; ++k) acc[k] += partials[(int64_t)b * 8 + k];
+  for (int k = 0; k < 8; ++k) s_red[k][tid] = acc[k];
+  __syncthreads();
+  for (int h = kObsThreads / 2; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int k = 0; k < 8; ++k) s_red[k][tid] += s_red[k][tid + h];
+    __syncthreads();
+  }
+  if (tid < 8) out[tid] = s_red[tid][0];
+}
+
+hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s) {
+  if (prec == 2) hipLaunchKernelGGL(obs_kernel<double>, dim3(blocks), dim3(kObsThreads), 0, s, a);
+  else hipLaunchKernelGGL(obs_kernel<float>, dim3(blocks), dim3(kObsThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, (const double *)a.partials, blocks, out8);
+  return hipGetLastError();
+}
+
+}  // namespace wp

@@ -1,0 +1,270 @@
+"""Thin ctypes binding of libwavepacket (include/wavepacket.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+kernels of the library.  PyTorch provides the device memory of the state and
+the stream the library enqueues on.  If the compiled library is missing the
+import fails: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwavepacket.so")
+
+WP_C64, WP_C128 = 1, 2
+PRECISIONS = {"c64": WP_C64, "c128": WP_C128}
+WAVE_KINDS = {"const": 0, "sin": 1, "cos": 2, "gauss_cos": 3, "sin2_cos": 4}
+V0_KINDS = {"none": 0, "softcore": 1, "morse": 2}
+ORDERS = {"vkv": 0, "kvk": 1}
+STATUS = {0: "WP_OK", -1: "WP_EINVAL", -2: "WP_ENOMEM", -3: "WP_EDEVICE",
+          -4: "WP_EUNSUPPORTED", -5: "WP_ESTATE"}
+OBSERVABLES = ("norm", "x", "y", "z", "x2", "y2", "z2", "energy")
+OBS_ALL = 0xFF
+
+
+class WavepacketError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)}" + (f" ({detail})" if detail else ""))
+
+
+class Waveform(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("A0", C.c_double), ("A1", C.c_double),
+                ("omega", C.c_double), ("phase", C.c_double), ("tc", C.c_double),
+                ("tau", C.c_double), ("ti", C.c_double), ("tf", C.c_double)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("prec", C.c_int32), ("n", C.c_uint64 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("mass", C.c_double),
+                ("hbar", C.c_double), ("dt", C.c_double)]
+
+
+class PotentialDesc(C.Structure):
+    _fields_ = [("a", Waveform * 3), ("b", Waveform * 3), ("c", Waveform), ("s", Waveform),
+                ("v0_kind", C.c_int32), ("v0_par", C.c_double * 4)]
+
+
+def _hip_runtimes() -> list:
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({l.split()[-1] for l in f if "libamdhip64" in l and "r-xp" in l})
+    except OSError:
+        return []
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # torch ships its own HIP runtime with the same soname as the system one.
+    # Loading torch first makes the dynamic loader resolve the library's HIP
+    # dependency to that same runtime, so torch's streams and allocations are
+    # valid handles for the library.  Two runtimes in one process would not
+    # share them.
+    import torch  # noqa: F401
+
+    L = C.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes are mapped in this process: {rts}")
+    P, vp, u64, d = C.POINTER, C.c_void_p, C.c_uint64, C.c_double
+    sig = {
+        "wp_state_bytes": [P(GridDesc), P(u64)],
+        "wp_workspace_bytes": [P(GridDesc), P(u64)],
+        "wp_create": [P(GridDesc), P(PotentialDesc), vp, P(vp)],
+        "wp_destroy": [vp],
+        "wp_bind_state": [vp, vp, u64],
+        "wp_set_state": [vp, vp, d],
+        "wp_set_state_gaussian": [vp, P(d), P(d), P(d), d],
+        "wp_propagate": [vp, u64],
+        "wp_set_order": [vp, C.c_int32],
+        "wp_get_state": [vp, vp, C.c_int32],
+        "wp_observables": [vp, C.c_uint32, P(d)],
+        "wp_get_time": [vp, P(d), P(u64)],
+        "wp_synchronize": [vp],
+        "wp_profile_propagate": [vp, u64, P(d), P(u64)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.wp_state_ptr.argtypes = [vp]
+    L.wp_state_ptr.restype = vp
+    L.wp_last_error.argtypes = [vp]
+    L.wp_last_error.restype = C.c_char_p
+    L.wp_version.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _wave(w) -> Waveform:
+    s = Waveform()
+    if w is None:
+        return s
+    s.kind = WAVE_KINDS[w.kind] if isinstance(w.kind, str) else int(w.kind)
+    for f in ("A0", "A1", "omega", "phase", "tc", "tau", "ti", "tf"):
+        setattr(s, f, float(getattr(w, f)))
+    return s
+
+
+def grid_desc(grid, precision: str) -> GridDesc:
+    g = GridDesc()
+    g.ndim = int(grid.ndim)
+    g.prec = PRECISIONS[precision]
+    n = list(grid.n) + [1] * (3 - len(grid.n))
+    lo = list(grid.lo) + [0.0] * (3 - len(grid.lo))
+    hi = list(grid.hi) + [1.0] * (3 - len(grid.hi))
+    for k in range(3):
+        g.n[k], g.lo[k], g.hi[k] = int(n[k]), float(lo[k]), float(hi[k])
+    g.mass, g.hbar, g.dt = float(grid.mass), float(grid.hbar), float(grid.dt)
+    return g
+
+
+def potential_desc(pot) -> PotentialDesc:
+    p = PotentialDesc()
+    for k in range(3):
+        p.a[k] = _wave(pot.a[k] if k < len(pot.a) else None)
+        p.b[k] = _wave(pot.b[k] if k < len(pot.b) else None)
+    p.c, p.s = _wave(pot.c), _wave(pot.s)
+    p.v0_kind = V0_KINDS[pot.v0_kind] if isinstance(pot.v0_kind, str) else int(pot.v0_kind)
+    par = list(pot.v0_par) + [0.0] * (4 - len(pot.v0_par))
+    for k in range(4):
+        p.v0_par[k] = float(par[k])
+    return p
+
+
+def state_bytes(grid, precision: str) -> int:
+    out = C.c_uint64()
+    rc = lib.wp_state_bytes(C.byref(grid_desc(grid, precision)), C.byref(out))
+    if rc:
+        raise WavepacketError(rc, "wp_state_bytes")
+    return out.value
+
+
+def workspace_bytes(grid, precision: str) -> int:
+    out = C.c_uint64()
+    rc = lib.wp_workspace_bytes(C.byref(grid_desc(grid, precision)), C.byref(out))
+    if rc:
+        raise WavepacketError(rc, "wp_workspace_bytes")
+    return out.value
+
+
+def _arr3(v, fill: float):
+    a = (C.c_double * 3)()
+    vals = list(v) + [fill] * (3 - len(v))
+    for k in range(3):
+        a[k] = float(vals[k])
+    return a
+
+
+class Simulation:
+    """One solver handle.  The state lives in a torch-allocated device buffer
+    bound to the handle; work is ordered on `stream` (a torch.cuda.Stream,
+    default: torch's current stream)."""
+
+    def __init__(self, grid, pot, precision: str = "c128", stream=None, order: str = "vkv"):
+        import torch  # device memory and streams only
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.grid, self.precision = grid, precision
+        self.shape = tuple((list(grid.n) + [1, 1, 1])[: int(grid.ndim)])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._g = grid_desc(grid, precision)
+        self._p = potential_desc(pot)
+        h = C.c_void_p()
+        rc = lib.wp_create(C.byref(self._g), C.byref(self._p), C.c_void_p(self.stream.cuda_stream),
+                           C.byref(h))
+        if rc:
+            raise WavepacketError(rc, "wp_create")
+        self._h = h
+        nbytes = state_bytes(grid, precision)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._check(lib.wp_bind_state(self._h, C.c_void_p(self.buffer.data_ptr()), nbytes), "wp_bind_state")
+        if order != "vkv":
+            self.set_order(order)
+
+    def _check(self, rc: int, what: str) -> None:
+        if rc:
+            raise WavepacketError(rc, what, lib.wp_last_error(self._h).decode())
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.wp_destroy(self._h)
+            self._h = None
+            self.buffer = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_order(self, order: str) -> None:
+        self._check(lib.wp_set_order(self._h, ORDERS[order]), "wp_set_order")
+
+    def set_state(self, psi: np.ndarray, t0: float = 0.0) -> None:
+        a = np.ascontiguousarray(psi, dtype=np.complex128)
+        if a.size != int(np.prod(self.shape)):
+            raise ValueError("state size does not match the grid")
+        self._check(lib.wp_set_state(self._h, C.c_void_p(a.ctypes.data), float(t0)), "wp_set_state")
+
+    def set_gaussian(self, center, sigma, k, t0: float = 0.0) -> None:
+        self._check(lib.wp_set_state_gaussian(self._h, _arr3(center, 0.0), _arr3(sigma, 1.0),
+                                              _arr3(k, 0.0), float(t0)), "wp_set_state_gaussian")
+
+    def propagate(self, nsteps: int) -> None:
+        self._check(lib.wp_propagate(self._h, int(nsteps)), "wp_propagate")
+
+    def get_state(self, as_precision: str = "c128") -> np.ndarray:
+        dt = np.complex128 if as_precision == "c128" else np.complex64
+        out = np.empty(self.shape, dtype=dt)
+        self._check(lib.wp_get_state(self._h, C.c_void_p(out.ctypes.data), PRECISIONS[as_precision]),
+                    "wp_get_state")
+        return out
+
+    def observables(self, mask: int = OBS_ALL) -> dict:
+        out = (C.c_double * 8)()
+        self._check(lib.wp_observables(self._h, int(mask), out), "wp_observables")
+        return {k: out[i] for i, k in enumerate(OBSERVABLES) if mask & (1 << i)}
+
+    def time(self):
+        t, n = C.c_double(), C.c_uint64()
+        self._check(lib.wp_get_time(self._h, C.byref(t), C.byref(n)), "wp_get_time")
+        return t.value, n.value
+
+    def synchronize(self) -> None:
+        self._check(lib.wp_synchronize(self._h), "wp_synchronize")
+
+    PASS_KINDS = ("solve1d", "axis0", "mid_fwd", "last", "mid_inv", "edge")
+
+    def profile_propagate(self, nsteps: int) -> dict:
+        """Propagate with a device-timed event pair around every kernel;
+        returns {kind: (launches, total_ms)} for the kinds that ran."""
+        ms = (C.c_double * 8)()
+        cnt = (C.c_uint64 * 8)()
+        self._check(lib.wp_profile_propagate(self._h, int(nsteps), ms, cnt), "wp_profile_propagate")
+        return {k: (cnt[i], ms[i]) for i, k in enumerate(self.PASS_KINDS) if cnt[i]}
+
+    def state_ptr(self) -> int:
+        return lib.wp_state_ptr(self._h)
+
+
+def from_problem(prob, precision: Optional[str] = None, stream=None, order: str = "vkv") -> Simulation:
+    """Create a Simulation for a workloads.Problem and set its Gaussian state."""
+    s = Simulation(prob.grid, prob.pot, precision or prob.precision, stream=stream, order=order)
+    s.set_gaussian(prob.init.center, prob.init.sigma, prob.init.k, prob.t0)
+    return s

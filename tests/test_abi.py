@@ -1,0 +1,106 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/*.h, and its host-side descriptor validation behaves as
+documented.  No kernel is launched here."""
+import ctypes as C
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1306_3247_amd", "libwavepacket.so")
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        names += re.findall(r"^[A-Za-z_][\w \*]*?\b(wp_\w+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libwavepacket.so is not built (run __graft_entry__.build())")
+    # Loaded through the binding so that the HIP runtime is torch's (see sim._load).
+    from paper_1306_3247_amd import sim
+
+    return sim.lib
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 16
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version(lib):
+    assert lib.wp_version().startswith(b"wavepacket")
+
+
+def _grid(**kw):
+    from paper_1306_3247_amd.workloads import Grid
+
+    g = Grid(3, [8, 16, 4], [-1.0] * 3, [1.0] * 3)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def _desc(grid, prec="c64"):
+    # Import the binding's structures without loading the library through it
+    # (the binding loads the same .so; that is fine on a host without GPU).
+    from paper_1306_3247_amd import sim
+
+    return sim.grid_desc(grid, prec)
+
+
+def _state_bytes(lib, desc):
+    out = C.c_uint64()
+    rc = lib.wp_state_bytes(C.byref(desc), C.byref(out))
+    return rc, out.value
+
+
+def test_state_and_workspace_bytes(lib):
+    d = _desc(_grid(), "c64")
+    rc, b = _state_bytes(lib, d)
+    assert rc == 0 and b == 8 * 16 * 4 * 8
+    d = _desc(_grid(), "c128")
+    rc, b = _state_bytes(lib, d)
+    assert rc == 0 and b == 8 * 16 * 4 * 16
+    out = C.c_uint64()
+    assert lib.wp_workspace_bytes(C.byref(d), C.byref(out)) == 0 and out.value > b
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=0), dict(ndim=4), dict(n=[6, 16, 4]), dict(n=[1, 16, 4]), dict(lo=[1.0, -1, -1]),
+    dict(mass=0.0), dict(mass=-1.0), dict(hbar=0.0), dict(dt=0.0), dict(dt=float("nan")),
+    dict(ndim=2),  # unused third axis must have n = 1
+])
+def test_invalid_grids_rejected(lib, bad):
+    rc, _ = _state_bytes(lib, _desc(_grid(**bad)))
+    assert rc == -1  # WP_EINVAL
+
+
+def test_invalid_precision_rejected(lib):
+    d = _desc(_grid())
+    d.prec = 3
+    rc, _ = _state_bytes(lib, d)
+    assert rc == -1
+
+
+def test_null_arguments(lib):
+    assert lib.wp_destroy(None) == -1
+    assert lib.wp_propagate(None, C.c_uint64(1)) == -1
+    assert lib.wp_last_error(None) == b"NULL handle"
+    out = C.c_void_p()
+    assert lib.wp_create(None, None, None, C.byref(out)) == -1
+
+
+def test_single_hip_runtime(lib):
+    from paper_1306_3247_amd import sim
+
+    assert len(sim._hip_runtimes()) == 1
