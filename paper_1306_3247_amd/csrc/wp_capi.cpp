@@ -120,6 +120,25 @@ double wavenumber(const wp_grid_desc &g, int d, uint64_t m) {
   return 2.0 * kPi * (double)mm / ((double)n * spacing(g, d));
 }
 
+// Twiddles of an n-point line transform in stage order: after a first
+// stage of radix r0 (2, 4 or 8) come radix-8 stages with Ls = r0, 8 r0, ...;
+// stage Ls holds exp(-2 pi i r k/(8 Ls)) at (r-1)*Ls + k, 1 <= r < 8, k < Ls.
+std::vector<cx<double>> stage_twiddles(uint64_t n) {
+  std::vector<cx<double>> tw;
+  if (n > 8) {
+    const int lg = ilog2(n);
+    const uint64_t r0 = (lg % 3 == 0) ? 8 : (uint64_t(1) << (lg % 3));
+    for (uint64_t ls = r0; ls < n; ls *= 8)
+      for (uint64_t r = 1; r < 8; ++r)
+        for (uint64_t k = 0; k < ls; ++k) {
+          const double ang = 2.0 * kPi * (double)(r * k) / (double)(8 * ls);
+          tw.push_back({std::cos(ang), -std::sin(ang)});
+        }
+  }
+  if (tw.empty()) tw.push_back({1.0, 0.0});
+  return tw;
+}
+
 wp::WaveDev to_dev(const wp_waveform &w) {
   wp::WaveDev d;
   d.kind = w.kind;
@@ -279,16 +298,8 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
   e = upload(&s->d_kfull, kf);
   if (e == hipSuccess) e = upload(&s->d_khalf, kh);
   if (e == hipSuccess) e = upload(&s->d_k2, k2);
-  // Twiddles exp(-2 pi i e/n) per axis.
-  for (int d = 0; d < 3 && e == hipSuccess; ++d) {
-    const uint64_t n = grid->n[d];
-    std::vector<cx<double>> tw(n);
-    for (uint64_t j = 0; j < n; ++j) {
-      const double ang = 2.0 * kPi * (double)j / (double)n;
-      tw[j] = {std::cos(ang), -std::sin(ang)};
-    }
-    e = upload(&s->d_tw[d], tw);
-  }
+  // Line-FFT twiddles per axis, in the stage order the kernels read them.
+  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = upload(&s->d_tw[d], stage_twiddles(grid->n[d]));
   if (e == hipSuccess) {
     int64_t b = (s->total + wp::kObsThreads - 1) / wp::kObsThreads;
     s->obs_blocks = (int)(b > 1024 ? 1024 : b);

@@ -119,24 +119,42 @@ __device__ __forceinline__ void dft(cx<R> *x) {
 // to (j - j mod Ls) R + (j mod Ls) + q Ls.  The first stage takes its inputs
 // straight from registers and the last leaves its outputs in registers, so a
 // transform of 8^s points exchanges through LDS s-1 times.  The first stage
-// has radix 2, 4 or 8 so that the rest are radix 8.
+// has radix 2, 4 or 8 so that the rest are radix 8; a thread does VPT/R
+// butterflies per stage.
 //
-// `Lds` maps an element index of this thread's line to an LDS reference.
-// Twiddles: tw[e] = exp(-2 pi i e / N) in FP64, e < N.
+// Twiddles are stored stage by stage ("stage order"): the stage with product
+// Ls > 1 owns 7*Ls entries at offset tw_offset(Ls), entry (r-1)*Ls + k being
+// exp(-2 pi i r k/(8 Ls)).  Lanes that run consecutive butterflies read
+// consecutive entries, which keeps the table reads free of bank conflicts.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int VPT_ = (N < 8 ? N : 8)>
 struct fft_shape {
   static constexpr int lg = __builtin_ctz(N);
-  static constexpr int VPT = N < 8 ? N : 8;
+  static constexpr int VPT = VPT_ < N ? VPT_ : N;
   static constexpr int L = N / VPT;
   static constexpr int R0 = (N <= 8) ? N : ((lg % 3 == 0) ? 8 : (1 << (lg % 3)));
+  static_assert(VPT >= R0 || N <= 8, "a thread must hold a whole first-stage butterfly");
 };
 
-template <int N, int RAD, int LS, bool INV, class R, class Lds>
-__device__ __forceinline__ void fft_stage(cx<R> (&v)[fft_shape<N>::VPT], int t,
-                                          const cx<double> *tw, Lds lds) {
-  constexpr int VPT = fft_shape<N>::VPT;
-  constexpr int L = fft_shape<N>::L;
+template <int N>
+constexpr int tw_offset(int LS) {
+  int off = 0;
+  for (int l = fft_shape<N>::R0; l < LS; l *= 8) off += 7 * l;
+  return off;
+}
+// Entries of the stage-ordered twiddle table of an N-point line.
+constexpr int tw_count(int N) {
+  if (N <= 8) return 1;
+  int lg = __builtin_ctz(N);
+  int r0 = (lg % 3 == 0) ? 8 : (1 << (lg % 3));
+  int off = 0;
+  for (int l = r0; l < N; l *= 8) off += 7 * l;
+  return off;
+}
+
+template <int N, int VPT, int RAD, int LS, bool INV, class R, class Lds>
+__device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
+  constexpr int L = N / VPT;
   constexpr int M = VPT / RAD;  // butterflies per thread
   constexpr bool LAST = (LS * RAD == N);
 #pragma unroll
@@ -147,9 +165,10 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[fft_shape<N>::VPT], int t,
 #pragma unroll
     for (int r = 0; r < RAD; ++r) x[r] = v[m + r * M];
     if constexpr (LS > 1) {
+      const cx<double> *tws = tw + tw_offset<N>(LS) + k;
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
-        cx<double> w = tw[(r * k) * (N / (LS * RAD))];
+        cx<double> w = tws[(r - 1) * LS];
         if (INV) w.y = -w.y;
         x[r] = mul_acc(x[r], w);
       }
@@ -165,30 +184,92 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[fft_shape<N>::VPT], int t,
   }
 }
 
-template <int N, int RAD, int LS, bool INV, class R, class Lds>
-__device__ __forceinline__ void fft_stages(cx<R> (&v)[fft_shape<N>::VPT], int t,
-                                           const cx<double> *tw, Lds lds) {
-  constexpr int L = fft_shape<N>::L;
-  constexpr int VPT = fft_shape<N>::VPT;
-  fft_stage<N, RAD, LS, INV>(v, t, tw, lds);
+template <int N, int VPT, int RAD, int LS, bool INV, class R, class Lds>
+__device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
+  constexpr int L = N / VPT;
+  fft_stage<N, VPT, RAD, LS, INV>(v, t, tw, lds);
   if constexpr (LS * RAD < N) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = lds(t + L * u);
     // The next stage writes LDS only if it is not the last one.
     if constexpr (LS * RAD * 8 < N) __syncthreads();
-    fft_stages<N, 8, LS * RAD, INV>(v, t, tw, lds);
+    fft_stages<N, VPT, 8, LS * RAD, INV>(v, t, tw, lds);
   }
 }
 
 // Whole line transform.  Every thread of the workgroup must call it (it
 // contains barriers) whether or not its line is valid.  It starts with a
 // barrier so that earlier LDS reads of the same buffer are complete.
-template <int N, bool INV, class R, class Lds>
-__device__ __forceinline__ void line_fft(cx<R> (&v)[fft_shape<N>::VPT], int t,
-                                         const cx<double> *tw, Lds lds) {
+template <int N, int VPT, bool INV, class R, class Lds>
+__device__ __forceinline__ void line_fft(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
   if constexpr (N > 8) __syncthreads();
-  fft_stages<N, fft_shape<N>::R0, 1, INV>(v, t, tw, lds);
+  fft_stages<N, VPT, fft_shape<N, VPT>::R0, 1, INV>(v, t, tw, lds);
+}
+
+// ---------------------------------------------------------------------------
+// exp(-i theta) to FP64 accuracy, for the phase factors evaluated at every
+// point: theta is reduced by the nearest multiple k of pi/2 with pi/2 split
+// in three parts (Cody and Waite's method; k * PIO2_A is exact for
+// |k| < 2^20), then sin and cos of the remainder |r| <= pi/4 come from their
+// Taylor series (terms to r^19 and r^18: truncation below 1e-17), and the
+// quadrant k mod 4 permutes and negates them.  Arguments beyond 1.5e6 rad go
+// to the library sincos.
+// ---------------------------------------------------------------------------
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+// Taylor coefficients 1/n!, evaluated by the compiler.
+template <int n>
+struct inv_fact {
+  static constexpr double value = 1.0 / fact(n);
+};
+
+// Large arguments: out of line, so that its registers do not count against
+// the common path.
+__device__ __noinline__ cx<double> expmi_large(double th) {
+  double s, c;
+  sincos(th, &s, &c);
+  return {c, -s};
+}
+
+__device__ __forceinline__ cx<double> expmi_taylor(double th) {
+  constexpr double TWO_OVER_PI = 0x1.45f306dc9c883p-1;
+  constexpr double PIO2_A = 0x1.921fb54400000p+0;
+  constexpr double PIO2_B = 0x1.0b4611a600000p-34;
+  constexpr double PIO2_C = 0x1.3198a2e037073p-69;
+  if (!(fabs(th) < 1.5e6)) return expmi_large(th);
+  const double k = rint(th * TWO_OVER_PI);
+  double r = fma(-k, PIO2_A, th);
+  r = fma(-k, PIO2_B, r);
+  r = fma(-k, PIO2_C, r);
+  const double r2 = r * r;
+  double ps = -inv_fact<19>::value;
+  ps = fma(ps, r2, inv_fact<17>::value);
+  ps = fma(ps, r2, -inv_fact<15>::value);
+  ps = fma(ps, r2, inv_fact<13>::value);
+  ps = fma(ps, r2, -inv_fact<11>::value);
+  ps = fma(ps, r2, inv_fact<9>::value);
+  ps = fma(ps, r2, -inv_fact<7>::value);
+  ps = fma(ps, r2, inv_fact<5>::value);
+  ps = fma(ps, r2, -inv_fact<3>::value);
+  const double sn = fma(ps * r2, r, r);
+  double pc = inv_fact<18>::value;
+  pc = fma(pc, r2, -inv_fact<16>::value);
+  pc = fma(pc, r2, inv_fact<14>::value);
+  pc = fma(pc, r2, -inv_fact<12>::value);
+  pc = fma(pc, r2, inv_fact<10>::value);
+  pc = fma(pc, r2, -inv_fact<8>::value);
+  pc = fma(pc, r2, inv_fact<6>::value);
+  pc = fma(pc, r2, -inv_fact<4>::value);
+  pc = fma(pc, r2, inv_fact<2>::value);
+  const double cs = fma(-pc, r2, 1.0);
+  // theta = k pi/2 + r: (cos, sin)(theta) for k mod 4 = 0, 1, 2, 3 is
+  // (c, s), (-s, c), (-c, -s), (s, -c).
+  const int q = (int)(long long)k & 3;
+  const double c1 = (q & 1) ? sn : cs;
+  const double s1 = (q & 1) ? cs : sn;
+  const double cosv = (q == 1 || q == 2) ? -c1 : c1;
+  const double sinv = (q >= 2) ? -s1 : s1;
+  return {cosv, -sinv};
 }
 
 // ---------------------------------------------------------------------------

@@ -9,208 +9,8 @@
 
 namespace wp {
 
-// ---------------------------------------------------------------------------
-// workgroup shape of a line pass
-// ---------------------------------------------------------------------------
-constexpr int pow2_floor(int x) {
-  int p = 1;
-  while (p * 2 <= x) p *= 2;
-  return p;
-}
-constexpr int imin(int a, int b) { return a < b ? a : b; }
-constexpr int imax(int a, int b) { return a > b ? a : b; }
-
-template <class R, int N, bool STRIDED>
-struct pass_cfg {
-  static constexpr int L = fft_shape<N>::L;
-  static constexpr int VPT = fft_shape<N>::VPT;
-  static constexpr int ELEM = (int)sizeof(cx<R>);
-  // One padding element after every 8 keeps the Stockham scatter of the
-  // first stage (stride 8 elements) off a single bank group.
-  static constexpr int NP = N + N / 8;
-  // Twiddles live in LDS up to 1024 points; longer lines read them from the
-  // (cached) global table so that the line data still fits.
-  static constexpr bool TW_LDS = N <= 1024;
-  // Lines per workgroup: about 32 KiB of line data, at least enough
-  // neighbouring lines (strided axes) that every row segment read is a full
-  // 128-byte cache line, at most 1024 threads and 96 KiB of line data.
-  static constexpr int T_MEM = imax(1, (32768 / ELEM) / N);
-  static constexpr int T_THR = 1024 / L;
-  static constexpr int T_LDS = imax(1, pow2_floor(98304 / (NP * ELEM)));
-  static constexpr int T_MIN = STRIDED ? 128 / ELEM : 1;
-  static constexpr int TILE = imin(imin(imax(T_MEM, T_MIN), T_THR), T_LDS);
-  static constexpr int THREADS = TILE * L;
-  static constexpr int LDS_ELEMS = (N > 8) ? TILE * NP : 1;
-};
-
-__device__ __forceinline__ void decode_line(const GridDev &g, int axis, int64_t o, int64_t c,
-                                            int idx[3]) {
-#pragma unroll
-  for (int d = 2; d >= 0; --d) {
-    if (d > axis) {
-      idx[d] = (int)(c & ((1 << g.lg[d]) - 1));
-      c >>= g.lg[d];
-    }
-  }
-#pragma unroll
-  for (int d = 2; d >= 0; --d) {
-    if (d < axis) {
-      idx[d] = (int)(o & ((1 << g.lg[d]) - 1));
-      o >>= g.lg[d];
-    }
-  }
-  idx[axis] = 0;
-}
-
-__device__ __forceinline__ double coord(const GridDev &g, int d, int i) {
-  return g.lo[d] + (double)i * g.dx[d];
-}
-
-// ---------------------------------------------------------------------------
-// line pass
-// ---------------------------------------------------------------------------
-template <class R, int N, bool STRIDED>
-__global__ void __launch_bounds__((pass_cfg<R, N, STRIDED>::THREADS)) pass_kernel(PassArgs a) {
-  using C = pass_cfg<R, N, STRIDED>;
-  using S = typename storage<R>::type;
-  constexpr int L = C::L, VPT = C::VPT, TILE = C::TILE, NT = C::THREADS;
-
-  __shared__ cx<R> s_data[C::LDS_ELEMS];
-  __shared__ cx<double> s_tw[C::TW_LDS ? N : 1];
-  __shared__ cx<double> s_tab[N];
-  __shared__ cx<double> s_line[TILE];
-  __shared__ double s_coef[CO_COUNT];
-
-  const int tid = threadIdx.x;
-  const int tau = STRIDED ? tid % TILE : tid / L;
-  const int t = STRIDED ? tid / TILE : tid % L;
-  const int64_t line = (int64_t)blockIdx.x * TILE + tau;
-  const bool valid = line < a.n_lines;
-  const int lgi = a.lg_inner;
-  const int64_t o = line >> lgi, c = line & (((int64_t)1 << lgi) - 1);
-  const int64_t base = (o << (fft_shape<N>::lg + lgi)) + c;
-  S *psi = (S *)a.psi;
-  const uint32_t ops = a.ops;
-
-  cx<R> v[VPT];
-  if (valid) {
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = load_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi));
-  } else {
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
-  }
-
-  if constexpr (C::TW_LDS)
-    for (int e = tid; e < N; e += NT) s_tw[e] = a.tw[e];
-  const cx<double> *tw = C::TW_LDS ? (const cx<double> *)s_tw : a.tw;
-  if ((ops & OP_V) && tid < CO_COUNT) s_coef[tid] = wave_value(a.pot.w[tid], time_of(a.time));
-  if (ops & OP_K) {
-    for (int e = tid; e < N; e += NT) s_tab[e] = a.ktab[a.axis][e];
-    if (tid < TILE) {
-      const int64_t l2 = (int64_t)blockIdx.x * TILE + tid;
-      if (l2 < a.n_lines) {
-        int idx[3];
-        decode_line(a.g, a.axis, l2 >> lgi, l2 & (((int64_t)1 << lgi) - 1), idx);
-        cx<double> f = {1.0, 0.0};
-        for (int d = 0; d < a.g.ndim; ++d)
-          if (d != a.axis) f = cmul(f, a.ktab[d][idx[d]]);
-        s_line[tid] = f;
-      }
-    }
-  }
-  __syncthreads();
-  const bool separable = a.pot.v0_kind == 0;
-  if ((ops & OP_V) && separable) {
-    const int ax = a.axis;
-    const double ca = s_coef[CO_A + ax], cb = s_coef[CO_B + ax];
-    for (int e = tid; e < N; e += NT) {
-      const double x = coord(a.g, ax, e);
-      s_tab[e] = expmi(a.vtau * (ca * x + cb * x * x));
-    }
-    if (tid < TILE) {
-      const int64_t l2 = (int64_t)blockIdx.x * TILE + tid;
-      if (l2 < a.n_lines) {
-        int idx[3];
-        decode_line(a.g, ax, l2 >> lgi, l2 & (((int64_t)1 << lgi) - 1), idx);
-        double th = s_coef[CO_C];
-        for (int d = 0; d < a.g.ndim; ++d) {
-          if (d == ax) continue;
-          const double x = coord(a.g, d, idx[d]);
-          th += s_coef[CO_A + d] * x + s_coef[CO_B + d] * x * x;
-        }
-        s_line[tid] = expmi(a.vtau * th);
-      }
-    }
-    __syncthreads();
-  }
-
-  auto lds = [&](int i) -> cx<R> & {
-    if constexpr (STRIDED) return s_data[(i + (i >> 3)) * TILE + tau];
-    else return s_data[tau * C::NP + i + (i >> 3)];
-  };
-
-  if (ops & OP_PRE_INV) line_fft<N, true>(v, t, tw, lds);
-  if (ops & OP_V) {
-    if (separable) {
-      const cx<double> fl = s_line[tau];
-#pragma unroll
-      for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_tab[t + L * u], fl));
-    } else {
-      int idx[3];
-      decode_line(a.g, a.axis, o, c, idx);
-      double xs[3];
-      for (int d = 0; d < 3; ++d) xs[d] = coord(a.g, d, idx[d]);
-#pragma unroll
-      for (int u = 0; u < VPT; ++u) {
-        xs[a.axis] = coord(a.g, a.axis, t + L * u);
-        double th = s_coef[CO_C];
-        for (int d = 0; d < a.g.ndim; ++d) th += s_coef[CO_A + d] * xs[d] + s_coef[CO_B + d] * xs[d] * xs[d];
-        th += s_coef[CO_S] * v0_value(a.pot, xs[0], xs[1], xs[2], a.g.ndim);
-        v[u] = mul_acc(v[u], expmi(a.vtau * th));
-      }
-    }
-  }
-  if (ops & OP_FWD) line_fft<N, false>(v, t, tw, lds);
-  if (ops & OP_K) {
-    const cx<double> fl = s_line[tau];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_tab[t + L * u], fl));
-  }
-  if (ops & OP_POST_INV) line_fft<N, true>(v, t, tw, lds);
-
-  if (valid) {
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) store_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
-  }
-}
-
-template <class R, int N, bool STRIDED>
-static hipError_t launch_pass_t(const PassArgs &a, hipStream_t s) {
-  using C = pass_cfg<R, N, STRIDED>;
-  const int64_t blocks = (a.n_lines + C::TILE - 1) / C::TILE;
-  hipLaunchKernelGGL((pass_kernel<R, N, STRIDED>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
-  return hipGetLastError();
-}
-
-template <class R, bool STRIDED>
-static hipError_t dispatch_pass(int lgN, const PassArgs &a, hipStream_t s) {
-  switch (lgN) {
-    case 1: return launch_pass_t<R, 2, STRIDED>(a, s);
-    case 2: return launch_pass_t<R, 4, STRIDED>(a, s);
-    case 3: return launch_pass_t<R, 8, STRIDED>(a, s);
-    case 4: return launch_pass_t<R, 16, STRIDED>(a, s);
-    case 5: return launch_pass_t<R, 32, STRIDED>(a, s);
-    case 6: return launch_pass_t<R, 64, STRIDED>(a, s);
-    case 7: return launch_pass_t<R, 128, STRIDED>(a, s);
-    case 8: return launch_pass_t<R, 256, STRIDED>(a, s);
-    case 9: return launch_pass_t<R, 512, STRIDED>(a, s);
-    case 10: return launch_pass_t<R, 1024, STRIDED>(a, s);
-    case 11: return launch_pass_t<R, 2048, STRIDED>(a, s);
-    case 12: return launch_pass_t<R, 4096, STRIDED>(a, s);
-    default: return hipErrorInvalidValue;
-  }
-}
+hipError_t dispatch_pass_c64(int lgN, const PassArgs &a, hipStream_t s);
+hipError_t dispatch_pass_c128(int lgN, const PassArgs &a, hipStream_t s);
 
 bool pass_supported(int prec, int lgN) { return (prec == 1 || prec == 2) && lgN >= 1 && lgN <= 12; }
 
@@ -218,9 +18,7 @@ hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s) {
   const int lgN = a.g.lg[a.axis];
   if (!pass_supported(prec, lgN)) return hipErrorInvalidValue;
   if ((a.ops & OP_V) && (a.ops & OP_K)) return hipErrorInvalidValue;
-  const bool strided = a.lg_inner > 0;
-  if (prec == 2) return strided ? dispatch_pass<double, true>(lgN, a, s) : dispatch_pass<double, false>(lgN, a, s);
-  return strided ? dispatch_pass<float, true>(lgN, a, s) : dispatch_pass<float, false>(lgN, a, s);
+  return prec == 2 ? dispatch_pass_c128(lgN, a, s) : dispatch_pass_c64(lgN, a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,6 +34,7 @@ template <class R, int N>
 __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a) {
   using S = typename storage<R>::type;
   constexpr int L = fft_shape<N>::L, VPT = fft_shape<N>::VPT;
+  static_assert(VPT <= 8, "one thread holds at most 8 values here");
   constexpr int NP = N + N / 8;
   __shared__ cx<R> s_data[N > 8 ? NP : 1];
   __shared__ double s_coef[CO_COUNT];
@@ -263,7 +62,7 @@ __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a)
     for (int u = 0; u < VPT; ++u) {
       double th = cc + (ca * xs[u] + cb * xs[u] * xs[u]);
       if (a.pot.v0_kind != 0) th += cs * v0_value(a.pot, xs[u], 0.0, 0.0, 1);
-      v[u] = mul_acc(v[u], expmi(vtau * th));
+      v[u] = mul_acc(v[u], expmi_taylor(vtau * th));
     }
   };
   auto apply_k = [&](bool half_factor) {
@@ -279,19 +78,19 @@ __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a)
   if (!kvk) {
     for (int64_t s = 0; s < ns; ++s) {
       if (s == 0) apply_v(step_time(a.time, 0, 0.0), a.vtau_half);
-      line_fft<N, false>(v, t, a.tw, lds);
+      line_fft<N, VPT, false>(v, t, a.tw, lds);
       apply_k(false);
-      line_fft<N, true>(v, t, a.tw, lds);
+      line_fft<N, VPT, true>(v, t, a.tw, lds);
       apply_v(step_time(a.time, s + 1, 0.0), s + 1 == ns ? a.vtau_half : a.vtau_full);
     }
   } else if (ns > 0) {
     // K/2 V K/2 with consecutive kinetic halves merged into full steps.
-    line_fft<N, false>(v, t, a.tw, lds);
+    line_fft<N, VPT, false>(v, t, a.tw, lds);
     apply_k(true);
     for (int64_t s = 0; s < ns; ++s) {
-      line_fft<N, true>(v, t, a.tw, lds);
+      line_fft<N, VPT, true>(v, t, a.tw, lds);
       apply_v(step_time(a.time, s, 0.5), a.vtau_full);
-      line_fft<N, false>(v, t, a.tw, lds);
+      line_fft<N, VPT, false>(v, t, a.tw, lds);
       if (s + 1 == ns) {
         apply_k(true);
       } else {
@@ -299,7 +98,7 @@ __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a)
         for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], a.kfull[t + L * u]);
       }
     }
-    line_fft<N, true>(v, t, a.tw, lds);
+    line_fft<N, VPT, true>(v, t, a.tw, lds);
   }
 #pragma unroll
   for (int u = 0; u < VPT; ++u) store_cx<R>(psi + t + L * u, v[u]);

@@ -1,0 +1,254 @@
+// wp_pass.hpp -- the line-pass kernel: every line along one axis is read from
+// HBM once, transformed in registers and LDS, and written back once.
+//
+// Three kinds of pass (template parameter KIND):
+//   PK_F  forward or inverse FFT only (middle axes of a 3D step);
+//   PK_V  [inverse FFT] potential phase [forward FFT] (first axis): the
+//         potential is evaluated on the device at the current time;
+//   PK_K  forward FFT, kinetic phase, inverse FFT (last axis).
+// Workgroup shapes are chosen per (precision, N, layout, kind) so that two or
+// more workgroups fit in a CU's 160 KiB of LDS, letting one workgroup load
+// while another computes.
+#pragma once
+#include "wp_internal.hpp"
+
+namespace wp {
+
+enum PassKind : int { PK_F = 0, PK_V = 1, PK_K = 2 };
+
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+constexpr int imin(int a, int b) { return a < b ? a : b; }
+constexpr int imax(int a, int b) { return a > b ? a : b; }
+
+template <class R, int N, bool STRIDED, int KIND>
+struct pass_cfg {
+  static constexpr int ELEM = (int)sizeof(cx<R>);
+  // 16 values per thread in FP32 (8 in FP64) halves the threads per line;
+  // potential passes keep 8, whose FP64 phase evaluation needs the registers.
+  static constexpr int VPT = (ELEM == 8 && N >= 16 && KIND != PK_V) ? 16 : (N < 8 ? N : 8);
+  static constexpr int L = N / VPT;
+  static constexpr bool EXCH = N > 8;  // more than one stage: exchanges through LDS
+  // One padding element after every 16 keeps the stage scatters spread over
+  // the banks.
+  static constexpr int NP = N >= 16 ? N + N / 16 : N;
+  static constexpr bool TW_LDS = N <= 512;
+  static constexpr int TW_BYTES = 16 * tw_count(N);
+  static constexpr int TAB_BYTES = KIND == PK_K ? 16 * N : 0;  // kinetic factors
+  // At most 80 KiB of LDS per workgroup (two per CU).
+  static constexpr int BUDGET = 81920 - 1024;
+  static constexpr int DATA_BUDGET = BUDGET - (TW_LDS ? TW_BYTES : 0) - TAB_BYTES;
+  static constexpr int T_LDS = EXCH ? imax(1, pow2_floor(DATA_BUDGET / (NP * ELEM))) : 4096;
+  static constexpr int T_THR = imax(1, 512 / L);
+  // Strided lines: enough neighbouring lines that each row segment read is
+  // a whole 128-byte cache line, within 512 threads.
+  static constexpr int T_MIN = STRIDED ? imin(128 / ELEM, imax(1, 512 / L)) : 1;
+  static constexpr int TILE = imin(T_LDS, imax(T_THR, T_MIN));
+  static constexpr int THREADS = TILE * L;
+  // Row segments shorter than a cache line: the two workgroups that share
+  // each line are placed on the same XCD (see pair_blocks).
+  static constexpr bool PAIR = STRIDED && TILE * ELEM < 128;
+  static_assert(THREADS <= 1024, "workgroup too large");
+  // Line data; a PK_V pass also stages its per-axis phase table here while
+  // the line data is in registers.
+  static constexpr int DATA_BYTES = imax(EXCH ? TILE * NP * ELEM : 0, KIND == PK_V ? 16 * N : 0);
+  // Waves per SIMD the register allocation must leave room for: two
+  // workgroups per CU (at most 128 VGPRs for 512-thread workgroups).
+  static constexpr int WAVES_EU = imax(1, imin(4, THREADS / 128));
+};
+
+__device__ __forceinline__ void decode_line(const GridDev &g, int axis, int64_t o, int64_t c, int idx[3]) {
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    if (d > axis) {
+      idx[d] = (int)(c & ((1 << g.lg[d]) - 1));
+      c >>= g.lg[d];
+    }
+  }
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    if (d < axis) {
+      idx[d] = (int)(o & ((1 << g.lg[d]) - 1));
+      o >>= g.lg[d];
+    }
+  }
+  idx[axis] = 0;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin (block b to XCD b mod 8),
+// each XCD with its own L2.  Within every 16 consecutive blocks this maps
+// blocks b and b+8, which share an XCD, to the adjacent tiles 2r and 2r+1,
+// so that a cache line split between two tiles is fetched into one L2.
+__device__ __forceinline__ unsigned pair_blocks(unsigned b, unsigned nblocks) {
+  if (nblocks % 16u != 0u) return b;
+  return (b & ~15u) | ((b & 7u) << 1) | ((b >> 3) & 1u);
+}
+
+__device__ __forceinline__ double coord(const GridDev &g, int d, int i) {
+  return g.lo[d] + (double)i * g.dx[d];
+}
+
+template <class R, int N, bool STRIDED, int KIND>
+__global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
+                                  (pass_cfg<R, N, STRIDED, KIND>::WAVES_EU))
+    pass_kernel(PassArgs a) {
+  using C = pass_cfg<R, N, STRIDED, KIND>;
+  using S = typename storage<R>::type;
+  constexpr int L = C::L, VPT = C::VPT, TILE = C::TILE, NT = C::THREADS;
+
+  __shared__ __align__(16) unsigned char s_raw[C::DATA_BYTES > 0 ? C::DATA_BYTES : 16];
+  __shared__ cx<double> s_tw[C::TW_LDS ? tw_count(N) : 1];
+  __shared__ cx<double> s_ktab[KIND == PK_K ? N : 1];
+  __shared__ double s_coef[CO_COUNT];
+  cx<R> *s_data = reinterpret_cast<cx<R> *>(s_raw);
+
+  const int tid = threadIdx.x;
+  const int tau = STRIDED ? tid % TILE : tid / L;
+  const int t = STRIDED ? tid / TILE : tid % L;
+  const unsigned blk = C::PAIR ? pair_blocks(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t line = (int64_t)blk * TILE + tau;
+  const bool valid = line < a.n_lines;
+  const int lgi = a.lg_inner;
+  const int64_t o = line >> lgi, c = line & (((int64_t)1 << lgi) - 1);
+  const int64_t base = (o << (fft_shape<N>::lg + lgi)) + c;
+  S *psi = (S *)a.psi;
+  const uint32_t ops = a.ops;
+
+  cx<R> v[VPT];
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = load_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi));
+  } else {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
+  }
+
+  if constexpr (C::TW_LDS)
+    for (int e = tid; e < tw_count(N); e += NT) s_tw[e] = a.tw[e];
+  const cx<double> *tw = C::TW_LDS ? (const cx<double> *)s_tw : a.tw;
+  if constexpr (KIND == PK_V)
+    if (tid < CO_COUNT) s_coef[tid] = wave_value(a.pot.w[tid], time_of(a.time));
+  if constexpr (KIND == PK_K) {
+    for (int e = tid; e < N; e += NT) s_ktab[e] = a.ktab[a.axis][e];
+    __syncthreads();
+  }
+
+  // Indices of this thread's line on the other axes.
+  int idx[3];
+  decode_line(a.g, a.axis, o, c, idx);
+
+  auto lds = [&](int i) -> cx<R> & {
+    if constexpr (STRIDED) return s_data[(i + (i >> 4)) * TILE + tau];
+    else return s_data[tau * C::NP + i + (i >> 4)];
+  };
+
+  if constexpr (KIND == PK_F) {
+    if (ops & OP_PRE_INV) line_fft<N, VPT, true>(v, t, tw, lds);
+    else line_fft<N, VPT, false>(v, t, tw, lds);
+  } else if constexpr (KIND == PK_K) {
+    // Kinetic factor of this line on the other axes (1/N is in the table of
+    // the last axis).
+    cx<double> kl = {1.0, 0.0};
+    for (int d = 0; d < a.g.ndim; ++d)
+      if (d != a.axis) kl = cmul(kl, a.ktab[d][idx[d]]);
+    line_fft<N, VPT, false>(v, t, tw, lds);
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_ktab[t + L * u], kl));
+    line_fft<N, VPT, true>(v, t, tw, lds);
+  } else {
+    __syncthreads();  // s_coef
+    const int ax = a.axis;
+    const double vt = a.vtau;
+    // phase = vt * (c + sum_d [a_d x_d + b_d x_d^2] + s V0(x)); the terms of
+    // the other axes are constant along the line.
+    double th_line = s_coef[CO_C], rho2 = 0.0;
+    for (int d = 0; d < a.g.ndim; ++d) {
+      if (d == ax) continue;
+      const double x = coord(a.g, d, idx[d]);
+      th_line += s_coef[CO_A + d] * x + s_coef[CO_B + d] * x * x;
+      rho2 += x * x;
+    }
+    th_line *= vt;
+    const double ca = vt * s_coef[CO_A + ax], cb = vt * s_coef[CO_B + ax];
+    const double lo = a.g.lo[ax], dx = a.g.dx[ax];
+    const bool separable = a.pot.v0_kind == 0;
+
+    if (ops & OP_PRE_INV) line_fft<N, VPT, true>(v, t, tw, lds);
+    if (separable) {
+      // Phase table of the line axis, staged in the (now idle) line buffer.
+      cx<double> *tab = reinterpret_cast<cx<double> *>(s_raw);
+      if constexpr (C::EXCH) __syncthreads();  // every thread is done with the line buffer
+      for (int e = tid; e < N; e += NT) {
+        const double x = lo + (double)e * dx;
+        tab[e] = expmi_taylor(x * fma(cb, x, ca));
+      }
+      const cx<double> fl = expmi_taylor(th_line);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(tab[t + L * u], fl));
+    } else {
+      const double cs = vt * s_coef[CO_S];
+      const int kind = a.pot.v0_kind;
+      const double p0 = a.pot.v0_par[0], p1 = a.pot.v0_par[1], p2 = a.pot.v0_par[2];
+      const double r2off = rho2 + p1;
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const double x = lo + (double)(t + L * u) * dx;
+        double th = th_line + x * fma(cb, x, ca);
+        if (kind == 1) {
+          th -= cs * p0 * rsqrt(fma(x, x, r2off));
+        } else {
+          const double e = 1.0 - exp(-p1 * (x - p2));
+          th += cs * p0 * e * e;
+        }
+        v[u] = mul_acc(v[u], expmi_taylor(th));
+      }
+    }
+    if (ops & OP_FWD) line_fft<N, VPT, false>(v, t, tw, lds);  // starts with a barrier
+  }
+
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) store_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
+  }
+}
+
+template <class R, int N, bool STRIDED, int KIND>
+hipError_t launch_pass_t(const PassArgs &a, hipStream_t s) {
+  using C = pass_cfg<R, N, STRIDED, KIND>;
+  const int64_t blocks = (a.n_lines + C::TILE - 1) / C::TILE;
+  hipLaunchKernelGGL((pass_kernel<R, N, STRIDED, KIND>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class R, int N>
+hipError_t launch_pass_n(const PassArgs &a, hipStream_t s) {
+  const bool strided = a.lg_inner > 0;
+  if (a.ops & OP_V) return strided ? launch_pass_t<R, N, true, PK_V>(a, s) : launch_pass_t<R, N, false, PK_V>(a, s);
+  if (a.ops & OP_K) return strided ? launch_pass_t<R, N, true, PK_K>(a, s) : launch_pass_t<R, N, false, PK_K>(a, s);
+  return strided ? launch_pass_t<R, N, true, PK_F>(a, s) : launch_pass_t<R, N, false, PK_F>(a, s);
+}
+
+template <class R>
+hipError_t dispatch_pass(int lgN, const PassArgs &a, hipStream_t s) {
+  switch (lgN) {
+    case 1: return launch_pass_n<R, 2>(a, s);
+    case 2: return launch_pass_n<R, 4>(a, s);
+    case 3: return launch_pass_n<R, 8>(a, s);
+    case 4: return launch_pass_n<R, 16>(a, s);
+    case 5: return launch_pass_n<R, 32>(a, s);
+    case 6: return launch_pass_n<R, 64>(a, s);
+    case 7: return launch_pass_n<R, 128>(a, s);
+    case 8: return launch_pass_n<R, 256>(a, s);
+    case 9: return launch_pass_n<R, 512>(a, s);
+    case 10: return launch_pass_n<R, 1024>(a, s);
+    case 11: return launch_pass_n<R, 2048>(a, s);
+    case 12: return launch_pass_n<R, 4096>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace wp

@@ -1,0 +1,8 @@
+// wp_pass_c64.hip -- line-pass kernels for the FP32 state.
+#include "wp_pass.hpp"
+
+namespace wp {
+
+hipError_t dispatch_pass_c64(int lgN, const PassArgs &a, hipStream_t s) { return dispatch_pass<float>(lgN, a, s); }
+
+}  // namespace wp
