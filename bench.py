@@ -100,6 +100,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--also-c64x", action="store_true", help="also time the FP32-state / FP64-arithmetic mode")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -141,15 +142,25 @@ def main() -> int:
     if not args.no_fp64:
         # Same start, same number of steps, FP64 state: the FP32 error of this run.
         s64, ms64, _ = time_gpu(S, prob, "c128", args.steps, args.warmup)
-        a = torch.view_as_real(s32.buffer.view(torch.complex64)).double()
         b = torch.view_as_real(s64.buffer.view(torch.complex128))
-        rel = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-        n32 = s32.observables(1)["norm"]
-        n64 = s64.observables(1)["norm"]
+
+        def err(sx):
+            a = torch.view_as_real(sx.buffer.view(torch.complex64)).double()
+            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)), \
+                abs(sx.observables(1)["norm"] - 1.0)
+
+        rel, drift = err(s32)
         out["fp64"] = {"value": sites * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                        "dtype": "f64"}
         out["accuracy"] = {"steps": args.warmup + args.steps, "rel_l2_f32_vs_f64": rel,
-                           "norm_drift_f32": abs(n32 - 1.0), "norm_drift_f64": abs(n64 - 1.0)}
+                           "norm_drift_f32": drift, "norm_drift_f64": abs(s64.observables(1)["norm"] - 1.0)}
+        if args.also_c64x:
+            sx, msx, _ = time_gpu(S, prob, "c64x", args.steps, args.warmup)
+            relx, driftx = err(sx)
+            out["c64x"] = {"value": sites * args.steps / (msx / 1e3), "ms_per_step": msx / args.steps,
+                           "dtype": "f64 arithmetic, f32 state", "rel_l2_vs_f64": relx, "norm_drift": driftx,
+                           "passes": {k: round(m / c, 4) for k, (c, m) in sx.profile_propagate(4).items()}}
+            sx.close()
         s64.close()
 
     # Roofline of the dominant kernel: every pass reads and writes the whole

@@ -24,7 +24,8 @@
  *     1D problems lie along x and 2D problems in the xy-plane (Section 2.2);
  *     unused axes have n = 1.  Boundaries are periodic.
  *   - State psi: row-major [n0][n1][n2] (last axis contiguous), interleaved
- *     (re, im).  WP_C128 stores two doubles per point, WP_C64 two floats.
+ *     (re, im).  WP_C128 stores two doubles per point, WP_C64 and WP_C64X
+ *     two floats.
  *     The FP32 path keeps phase arguments, coordinates, time and every
  *     reduction in FP64 and multiplies by FP64-accurate factors.
  *   - Streams: all device work of a handle is ordered on the HIP stream
@@ -57,7 +58,12 @@ typedef enum {
   WP_ESTATE = -5        /* call not allowed in the handle's current state     */
 } wp_status;
 
-typedef enum { WP_C64 = 1, WP_C128 = 2 } wp_precision;
+/* WP_C64: FP32 state; FFT additions in FP32, every multiply by a twiddle or
+ *   phase factor done with the FP64 factor and rounded once.
+ * WP_C64X: FP32 state; all arithmetic of a pass in FP64, rounded to FP32
+ *   when the pass stores the state.
+ * WP_C128: FP64 state and arithmetic. */
+typedef enum { WP_C64 = 1, WP_C128 = 2, WP_C64X = 3 } wp_precision;
 
 /* Operator order of a step.  WP_ORDER_VKV is the default described above.
  * WP_ORDER_KVK is eq. splitop as printed: kinetic half step, potential at the
@@ -181,7 +187,8 @@ wp_status wp_propagate(wp_sim *sim, uint64_t nsteps);
 wp_status wp_set_order(wp_sim *sim, int32_t order);
 
 /* Copy the state at the current time to host memory as interleaved
- * complex128 (as_prec = WP_C128) or complex64 (WP_C64).  Synchronises. */
+ * complex128 (as_prec = WP_C128) or complex64 (WP_C64; WP_C64X is not a
+ * valid output format).  Synchronises. */
 wp_status wp_get_state(wp_sim *sim, void *host_out, int32_t as_prec);
 
 /* FP64 observables of the current state at the current time (Table 3 and
@@ -199,7 +206,8 @@ enum {
   WP_PASS_LAST = 3,     /* last axis: FFT, kinetic phase, inverse FFT          */
   WP_PASS_MID_INV = 4,  /* middle axis (3D): inverse FFT                       */
   WP_PASS_EDGE = 5,     /* first-axis pass opening or closing a propagation    */
-  WP_PASS_KINDS = 6
+  WP_PASS_COEF = 6,     /* waveform values of the potential for a run of steps */
+  WP_PASS_KINDS = 7
 };
 
 /* Same work as wp_propagate(sim, nsteps) (the state advances identically),

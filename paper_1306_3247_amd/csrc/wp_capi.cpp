@@ -30,6 +30,7 @@ struct wp_sim {
   double *d_k2 = nullptr;                              // k^2 per axis, n0+n1+n2
   cx<double> *d_tw[3] = {nullptr, nullptr, nullptr};
   double *d_partials = nullptr, *d_out8 = nullptr;
+  double *d_coef = nullptr;  // waveform values for up to kCoefChunk steps
   int obs_blocks = 1;
   double t0 = 0.0;
   uint64_t step = 0;
@@ -73,7 +74,7 @@ bool wave_ok(const wp_waveform &w) {
 std::string check_grid(const wp_grid_desc *g) {
   if (!g) return "grid descriptor is NULL";
   if (g->ndim < 1 || g->ndim > 3) return "ndim must be 1, 2 or 3";
-  if (g->prec != WP_C64 && g->prec != WP_C128) return "prec must be WP_C64 or WP_C128";
+  if (g->prec != WP_C64 && g->prec != WP_C128 && g->prec != WP_C64X) return "prec must be WP_C64, WP_C64X or WP_C128";
   for (int d = 0; d < 3; ++d) {
     if (d < g->ndim) {
       if (g->n[d] < 2 || !is_pow2(g->n[d])) return "n on a used axis must be a power of two >= 2";
@@ -156,7 +157,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 
 uint64_t table_bytes(const wp_grid_desc &g) {
   uint64_t axes = g.n[0] + g.n[1] + g.n[2];
-  return axes * (16 + 16 + 8 + 16) + 1024 * 8 * 8 + 64;
+  return axes * (16 + 16 + 8 + 16) + 1024 * 8 * 8 + 64 + 8 * wp::CO_COUNT * wp::kCoefChunk;
 }
 
 void release(wp_sim *s) {
@@ -169,7 +170,11 @@ void release(wp_sim *s) {
     if (p) (void)hipFree(p);
   if (s->d_partials) (void)hipFree(s->d_partials);
   if (s->d_out8) (void)hipFree(s->d_out8);
+  if (s->d_coef) (void)hipFree(s->d_coef);
 }
+
+// Precision of the stored state (WP_C64X keeps an FP32 state).
+int storage_prec(const wp_sim *s) { return s->prec == WP_C128 ? WP_C128 : WP_C64; }
 
 // The state buffer is allocated on first use unless the caller bound one.
 hipError_t ensure_state(wp_sim *s) {
@@ -198,11 +203,7 @@ wp::PassArgs pass_args(const wp_sim *s, int axis, uint32_t ops) {
   a.lg_inner = lgi;
   a.n_lines = s->total >> s->lg[axis];
   a.ops = ops;
-  a.time.t0 = s->t0;
-  a.time.dt = s->g.dt;
-  a.time.step = 0;
-  a.time.step_dev = nullptr;
-  a.time.half = 0.0;
+  a.coef = nullptr;
   a.vtau = 0.0;
   a.pot = s->pd;
   int off = 0;
@@ -232,7 +233,7 @@ const char *wp_last_error(const wp_sim *sim) { return sim ? sim->err.c_str() : "
 
 wp_status wp_state_bytes(const wp_grid_desc *grid, uint64_t *bytes) {
   if (!bytes || !check_grid(grid).empty()) return WP_EINVAL;
-  const uint64_t elem = grid->prec == WP_C64 ? 8 : 16;
+  const uint64_t elem = grid->prec == WP_C128 ? 16 : 8;
   *bytes = grid->n[0] * grid->n[1] * grid->n[2] * elem;
   return WP_OK;
 }
@@ -306,6 +307,7 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
     e = hipMalloc((void **)&s->d_partials, sizeof(double) * 8 * (size_t)s->obs_blocks);
   }
   if (e == hipSuccess) e = hipMalloc((void **)&s->d_out8, sizeof(double) * 8);
+  if (e == hipSuccess) e = hipMalloc((void **)&s->d_coef, sizeof(double) * wp::CO_COUNT * wp::kCoefChunk);
   if (e == hipSuccess) wp_state_bytes(grid, &s->psi_bytes);
   if (e != hipSuccess) {
     release(s);
@@ -404,7 +406,7 @@ wp_status wp_set_state_gaussian(wp_sim *s, const double center[3], const double 
   if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
   cx<double> *d[3] = {nullptr, nullptr, nullptr};
   for (int i = 0; i < 3 && e == hipSuccess; ++i) e = upload(&d[i], f[i]);
-  if (e == hipSuccess) e = wp::launch_gaussian(s->prec, s->psi, s->gd, d[0], d[1], d[2], s->stream);
+  if (e == hipSuccess) e = wp::launch_gaussian(storage_prec(s), s->psi, s->gd, d[0], d[1], d[2], s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   for (auto p : d)
     if (p) (void)hipFree(p);
@@ -436,6 +438,29 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
   hipStream_t st = s->stream;
   auto pass = [&](int kind, const wp::PassArgs &a) {
     return launch(kind, [&]() { return wp::launch_pass(prec, a, st); });
+  };
+  // The potential's waveform values come from a table filled for up to
+  // kCoefChunk consecutive step times at once; the stream orders each refill
+  // after the passes that read the previous contents.
+  int64_t cbase = -1;
+  double chalf = 0.0;
+  auto coef_at = [&](int64_t n, double half, const double **out) -> hipError_t {
+    if (cbase < 0 || half != chalf || n < cbase || n >= cbase + wp::kCoefChunk) {
+      wp::TimeDev T{};
+      T.t0 = s->t0;
+      T.dt = s->g.dt;
+      T.step = n;
+      T.step_dev = nullptr;
+      T.half = half;
+      hipError_t r = launch(WP_PASS_COEF, [&]() {
+        return wp::launch_coefficients(s->pd, T, wp::kCoefChunk, s->d_coef, st);
+      });
+      if (r != hipSuccess) return r;
+      cbase = n;
+      chalf = half;
+    }
+    *out = s->d_coef + (n - cbase) * wp::CO_COUNT;
+    return hipSuccess;
   };
   if (s->g.ndim == 1) {
     wp::Solve1DArgs a{};
@@ -474,17 +499,17 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
     // [V/2(t_n) F_0] ([middle] [F_0^-1 V(t_n+1) F_0])* ... [F_0^-1 V/2(t_N)]:
     // equal-time potential halves of consecutive steps are merged.
     wp::PassArgs a0 = pass_args(s, 0, wp::OP_V | wp::OP_FWD);
-    a0.time.step = (int64_t)s->step;
+    e = coef_at((int64_t)s->step, 0.0, &a0.coef);
     a0.vtau = tau_half;
-    e = pass(WP_PASS_EDGE, a0);
+    if (e == hipSuccess) e = pass(WP_PASS_EDGE, a0);
     for (uint64_t j = 0; j < nsteps && e == hipSuccess; ++j) {
       e = middle(false);
       if (e != hipSuccess) break;
       const bool lastj = (j + 1 == nsteps);
       wp::PassArgs a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | (lastj ? 0u : wp::OP_FWD));
-      a.time.step = (int64_t)(s->step + j + 1);
+      e = coef_at((int64_t)(s->step + j + 1), 0.0, &a.coef);
       a.vtau = lastj ? tau_half : tau_full;
-      e = pass(lastj ? WP_PASS_EDGE : WP_PASS_AXIS0, a);
+      if (e == hipSuccess) e = pass(lastj ? WP_PASS_EDGE : WP_PASS_AXIS0, a);
     }
   } else {
     // K/2 V(t_n + dt/2) K/2 with consecutive kinetic halves merged.
@@ -492,10 +517,9 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
     if (e == hipSuccess) e = middle(true);
     for (uint64_t j = 0; j < nsteps && e == hipSuccess; ++j) {
       wp::PassArgs a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | wp::OP_FWD);
-      a.time.step = (int64_t)(s->step + j);
-      a.time.half = 0.5;
+      e = coef_at((int64_t)(s->step + j), 0.5, &a.coef);
       a.vtau = tau_full;
-      e = pass(WP_PASS_AXIS0, a);
+      if (e == hipSuccess) e = pass(WP_PASS_AXIS0, a);
       if (e == hipSuccess) e = middle(j + 1 == nsteps);
     }
     if (e == hipSuccess) e = pass(WP_PASS_EDGE, pass_args(s, 0, wp::OP_PRE_INV));
@@ -572,10 +596,10 @@ wp_status wp_get_state(wp_sim *s, void *host_out, int32_t as_prec) {
   (void)hipSetDevice(s->device);
   hipError_t e = ensure_state(s);
   if (e != hipSuccess) return state_fail(s, e, "get_state");
-  if (as_prec == s->prec) {
+  if (as_prec == storage_prec(s)) {
     e = hipMemcpyAsync(host_out, s->psi, s->psi_bytes, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  } else if (s->prec == WP_C64) {
+  } else if (storage_prec(s) == WP_C64) {
     std::vector<float> tmp(2 * (size_t)s->total);
     e = hipMemcpyAsync(tmp.data(), s->psi, s->psi_bytes, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -614,7 +638,7 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
   a.pot = s->pd;
   a.partials = s->d_partials;
   double sums[8], ksum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  hipError_t e = wp::launch_observables(s->prec, a, s->obs_blocks, s->d_out8, s->stream);
+  hipError_t e = wp::launch_observables(storage_prec(s), a, s->obs_blocks, s->d_out8, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(sums, s->d_out8, sizeof(sums), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e == hipSuccess && energy) {
@@ -641,7 +665,7 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
         k.k2tab[d] = s->d_k2 + off;
         off += (int)s->g.n[d];
       }
-      e = wp::launch_observables(s->prec, k, s->obs_blocks, s->d_out8, s->stream);
+      e = wp::launch_observables(storage_prec(s), k, s->obs_blocks, s->d_out8, s->stream);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(ksum, s->d_out8, sizeof(ksum), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);

@@ -152,6 +152,14 @@ constexpr int tw_count(int N) {
   return off;
 }
 
+// LDS position of element i of a line: one padding slot after every 16
+// elements.  In every index pattern of the stages below, the low four bits
+// never carry when a multiple of Ls (writes) or of L (reads) is added, so
+// pad(a + c) = pad(a) + c + (c >> 4) for those offsets c: each thread
+// computes one base per butterfly and every other position is a constant
+// offset (an immediate in the LDS instruction).
+__device__ __forceinline__ constexpr int pad16(int i) { return i + (i >> 4); }
+
 template <int N, int VPT, int RAD, int LS, bool INV, class R, class Lds>
 __device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
   constexpr int L = N / VPT;
@@ -178,8 +186,9 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const cx<doubl
 #pragma unroll
       for (int q = 0; q < RAD; ++q) v[m + q * M] = x[q];
     } else {
+      const int p0 = pad16((j - k) * RAD + k);
 #pragma unroll
-      for (int q = 0; q < RAD; ++q) lds((j - k) * RAD + k + q * LS) = x[q];
+      for (int q = 0; q < RAD; ++q) lds(p0 + q * LS + ((q * LS) >> 4)) = x[q];
     }
   }
 }
@@ -190,8 +199,9 @@ __device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const cx<doub
   fft_stage<N, VPT, RAD, LS, INV>(v, t, tw, lds);
   if constexpr (LS * RAD < N) {
     __syncthreads();
+    const int pt = pad16(t);
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = lds(t + L * u);
+    for (int u = 0; u < VPT; ++u) v[u] = lds(pt + L * u + ((L * u) >> 4));
     // The next stage writes LDS only if it is not the last one.
     if constexpr (LS * RAD * 8 < N) __syncthreads();
     fft_stages<N, VPT, 8, LS * RAD, INV>(v, t, tw, lds);
@@ -201,6 +211,8 @@ __device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const cx<doub
 // Whole line transform.  Every thread of the workgroup must call it (it
 // contains barriers) whether or not its line is valid.  It starts with a
 // barrier so that earlier LDS reads of the same buffer are complete.
+// `Lds` maps a padded position (see pad16) of this thread's line to an LDS
+// reference.
 template <int N, int VPT, bool INV, class R, class Lds>
 __device__ __forceinline__ void line_fft(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
   if constexpr (N > 8) __syncthreads();
@@ -229,6 +241,45 @@ __device__ __noinline__ cx<double> expmi_large(double th) {
   double s, c;
   sincos(th, &s, &c);
   return {c, -s};
+}
+
+// |theta| <= pi/4: no reduction needed (the same series as below).
+__device__ __forceinline__ cx<double> expmi_quarter(double r) {
+  const double r2 = r * r;
+  double ps = -inv_fact<19>::value;
+  ps = fma(ps, r2, inv_fact<17>::value);
+  ps = fma(ps, r2, -inv_fact<15>::value);
+  ps = fma(ps, r2, inv_fact<13>::value);
+  ps = fma(ps, r2, -inv_fact<11>::value);
+  ps = fma(ps, r2, inv_fact<9>::value);
+  ps = fma(ps, r2, -inv_fact<7>::value);
+  ps = fma(ps, r2, inv_fact<5>::value);
+  ps = fma(ps, r2, -inv_fact<3>::value);
+  double pc = inv_fact<18>::value;
+  pc = fma(pc, r2, -inv_fact<16>::value);
+  pc = fma(pc, r2, inv_fact<14>::value);
+  pc = fma(pc, r2, -inv_fact<12>::value);
+  pc = fma(pc, r2, inv_fact<10>::value);
+  pc = fma(pc, r2, -inv_fact<8>::value);
+  pc = fma(pc, r2, inv_fact<6>::value);
+  pc = fma(pc, r2, -inv_fact<4>::value);
+  pc = fma(pc, r2, inv_fact<2>::value);
+  return {fma(-pc, r2, 1.0), -fma(ps * r2, r, r)};
+}
+
+// |theta| <= 1/16: the series to r^9 and r^10 (next terms below 1e-20).
+__device__ __forceinline__ cx<double> expmi_tiny(double r) {
+  const double r2 = r * r;
+  double ps = inv_fact<9>::value;
+  ps = fma(ps, r2, -inv_fact<7>::value);
+  ps = fma(ps, r2, inv_fact<5>::value);
+  ps = fma(ps, r2, -inv_fact<3>::value);
+  double pc = -inv_fact<10>::value;
+  pc = fma(pc, r2, inv_fact<8>::value);
+  pc = fma(pc, r2, -inv_fact<6>::value);
+  pc = fma(pc, r2, inv_fact<4>::value);
+  pc = fma(pc, r2, -inv_fact<2>::value);
+  return {fma(pc, r2, 1.0), -fma(ps * r2, r, r)};
 }
 
 __device__ __forceinline__ cx<double> expmi_taylor(double th) {
@@ -271,6 +322,18 @@ __device__ __forceinline__ cx<double> expmi_taylor(double th) {
   const double sinv = (q >= 2) ? -s1 : s1;
   return {cosv, -sinv};
 }
+
+// exp(-i theta) choosing, for the whole wavefront at once (the branches stay
+// uniform), the cheapest of the three evaluations that is exact for every
+// lane's argument.  Phase increments per step are usually small, so the
+// short series is the common case.
+__device__ __forceinline__ cx<double> expmi_wave(double th) {
+  const double a = fabs(th);
+  if (__all(a <= 0.0625)) return expmi_tiny(th);
+  if (__all(a <= 0.78539816339744830962)) return expmi_quarter(th);
+  return expmi_taylor(th);
+}
+
 
 // ---------------------------------------------------------------------------
 // time-dependent potential
@@ -343,14 +406,16 @@ struct storage<float> {
   using type = float2;
 };
 
-template <class R>
-__device__ __forceinline__ cx<R> load_cx(const typename storage<R>::type *p) {
-  typename storage<R>::type v = *p;
-  return {v.x, v.y};
+// Load a stored complex value (float2 or double2) into the compute type, and
+// store back with one rounding.
+template <class R, class T>
+__device__ __forceinline__ cx<R> load_as(const T *p) {
+  const T v = *p;
+  return {(R)v.x, (R)v.y};
 }
-template <class R>
-__device__ __forceinline__ void store_cx(typename storage<R>::type *p, cx<R> v) {
-  typename storage<R>::type s;
+template <class R, class T>
+__device__ __forceinline__ void store_from(T *p, cx<R> v) {
+  T s;
   s.x = v.x;
   s.y = v.y;
   *p = s;

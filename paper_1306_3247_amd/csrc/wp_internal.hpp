@@ -44,8 +44,8 @@ struct PassArgs {
   int32_t lg_inner;  // log2 of the product of the axis lengths after `axis`
   int64_t n_lines;
   uint32_t ops;
-  TimeDev time;      // when OP_V
-  double vtau;       // phase = V * vtau (dt/2hbar or dt/hbar)
+  const double *coef;  // OP_V: the CO_COUNT waveform values at this pass's time
+  double vtau;         // phase = V * vtau (dt/2hbar or dt/hbar)
   PotDev pot;
   const cx<double> *ktab[3];  // kinetic factors per axis (OP_K)
   const cx<double> *tw;       // twiddles exp(-2 pi i e/N), e < N
@@ -85,12 +85,16 @@ hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<doubl
 hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src, int64_t count,
                           hipStream_t s);
 hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s);
+// Waveform values for `count` consecutive steps: out[j*CO_COUNT + w] is
+// waveform w at the time of step T.step + j (plus T.half).
+hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, double *out, hipStream_t s);
 
 // Largest line length (points) supported by the line-pass kernels and by the
 // single-workgroup 1D solver.
 constexpr int kMaxLinePass = 4096;
 constexpr int kMaxLine1D = 8192;
 constexpr int kObsThreads = 256;
+constexpr int kCoefChunk = 1024;  // steps per coefficient table
 
 bool pass_supported(int prec, int lgN);
 

@@ -10,15 +10,18 @@
 namespace wp {
 
 hipError_t dispatch_pass_c64(int lgN, const PassArgs &a, hipStream_t s);
+hipError_t dispatch_pass_c64x(int lgN, const PassArgs &a, hipStream_t s);
 hipError_t dispatch_pass_c128(int lgN, const PassArgs &a, hipStream_t s);
 
-bool pass_supported(int prec, int lgN) { return (prec == 1 || prec == 2) && lgN >= 1 && lgN <= 12; }
+bool pass_supported(int prec, int lgN) { return prec >= 1 && prec <= 3 && lgN >= 1 && lgN <= 12; }
 
 hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s) {
   const int lgN = a.g.lg[a.axis];
   if (!pass_supported(prec, lgN)) return hipErrorInvalidValue;
   if ((a.ops & OP_V) && (a.ops & OP_K)) return hipErrorInvalidValue;
-  return prec == 2 ? dispatch_pass_c128(lgN, a, s) : dispatch_pass_c64(lgN, a, s);
+  if (prec == 2) return dispatch_pass_c128(lgN, a, s);
+  if (prec == 3) return dispatch_pass_c64x(lgN, a, s);
+  return dispatch_pass_c64(lgN, a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -30,16 +33,16 @@ __device__ __forceinline__ double step_time(const TimeDev &T, int64_t s, double 
   return T.t0 + ((double)n + half) * T.dt;
 }
 
-template <class R, int N>
+template <class S, class R, int N>
 __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a) {
-  using S = typename storage<R>::type;
+  using T = typename storage<S>::type;
   constexpr int L = fft_shape<N>::L, VPT = fft_shape<N>::VPT;
   static_assert(VPT <= 8, "one thread holds at most 8 values here");
-  constexpr int NP = N + N / 8;
+  constexpr int NP = N >= 16 ? N + N / 16 : N;
   __shared__ cx<R> s_data[N > 8 ? NP : 1];
   __shared__ double s_coef[CO_COUNT];
   const int t = threadIdx.x;
-  S *psi = (S *)a.psi;
+  T *psi = (T *)a.psi;
 
   cx<R> v[VPT];
   cx<double> kf[VPT];
@@ -47,11 +50,11 @@ __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a)
   const bool kvk = a.order == 1;
 #pragma unroll
   for (int u = 0; u < VPT; ++u) {
-    v[u] = load_cx<R>(psi + t + L * u);
+    v[u] = load_as<R>(psi + t + L * u);
     kf[u] = kvk ? a.khalf[t + L * u] : a.kfull[t + L * u];
     xs[u] = a.g.lo[0] + (double)(t + L * u) * a.g.dx[0];
   }
-  auto lds = [&](int i) -> cx<R> & { return s_data[i + (i >> 3)]; };
+  auto lds = [&](int p) -> cx<R> & { return s_data[p]; };
 
   auto apply_v = [&](double time, double vtau) {
     __syncthreads();
@@ -62,7 +65,7 @@ __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a)
     for (int u = 0; u < VPT; ++u) {
       double th = cc + (ca * xs[u] + cb * xs[u] * xs[u]);
       if (a.pot.v0_kind != 0) th += cs * v0_value(a.pot, xs[u], 0.0, 0.0, 1);
-      v[u] = mul_acc(v[u], expmi_taylor(vtau * th));
+      v[u] = mul_acc(v[u], expmi_wave(vtau * th));
     }
   };
   auto apply_k = [&](bool half_factor) {
@@ -101,38 +104,56 @@ __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a)
     line_fft<N, VPT, true>(v, t, a.tw, lds);
   }
 #pragma unroll
-  for (int u = 0; u < VPT; ++u) store_cx<R>(psi + t + L * u, v[u]);
+  for (int u = 0; u < VPT; ++u) store_from(psi + t + L * u, v[u]);
 }
 
-template <class R, int N>
+template <class S, class R, int N>
 static hipError_t launch_solve1d_t(const Solve1DArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((solve1d_kernel<R, N>), dim3(1), dim3(fft_shape<N>::L), 0, s, a);
+  hipLaunchKernelGGL((solve1d_kernel<S, R, N>), dim3(1), dim3(fft_shape<N>::L), 0, s, a);
   return hipGetLastError();
 }
 
-template <class R>
+template <class S, class R>
 static hipError_t dispatch_solve1d(int lgN, const Solve1DArgs &a, hipStream_t s) {
   switch (lgN) {
-    case 1: return launch_solve1d_t<R, 2>(a, s);
-    case 2: return launch_solve1d_t<R, 4>(a, s);
-    case 3: return launch_solve1d_t<R, 8>(a, s);
-    case 4: return launch_solve1d_t<R, 16>(a, s);
-    case 5: return launch_solve1d_t<R, 32>(a, s);
-    case 6: return launch_solve1d_t<R, 64>(a, s);
-    case 7: return launch_solve1d_t<R, 128>(a, s);
-    case 8: return launch_solve1d_t<R, 256>(a, s);
-    case 9: return launch_solve1d_t<R, 512>(a, s);
-    case 10: return launch_solve1d_t<R, 1024>(a, s);
-    case 11: return launch_solve1d_t<R, 2048>(a, s);
-    case 12: return launch_solve1d_t<R, 4096>(a, s);
-    case 13: return launch_solve1d_t<R, 8192>(a, s);
+    case 1: return launch_solve1d_t<S, R, 2>(a, s);
+    case 2: return launch_solve1d_t<S, R, 4>(a, s);
+    case 3: return launch_solve1d_t<S, R, 8>(a, s);
+    case 4: return launch_solve1d_t<S, R, 16>(a, s);
+    case 5: return launch_solve1d_t<S, R, 32>(a, s);
+    case 6: return launch_solve1d_t<S, R, 64>(a, s);
+    case 7: return launch_solve1d_t<S, R, 128>(a, s);
+    case 8: return launch_solve1d_t<S, R, 256>(a, s);
+    case 9: return launch_solve1d_t<S, R, 512>(a, s);
+    case 10: return launch_solve1d_t<S, R, 1024>(a, s);
+    case 11: return launch_solve1d_t<S, R, 2048>(a, s);
+    case 12: return launch_solve1d_t<S, R, 4096>(a, s);
+    case 13: return launch_solve1d_t<S, R, 8192>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s) {
   const int lgN = a.g.lg[0];
-  return prec == 2 ? dispatch_solve1d<double>(lgN, a, s) : dispatch_solve1d<float>(lgN, a, s);
+  if (prec == 2) return dispatch_solve1d<double, double>(lgN, a, s);
+  if (prec == 3) return dispatch_solve1d<float, double>(lgN, a, s);
+  return dispatch_solve1d<float, float>(lgN, a, s);
+}
+
+// ---------------------------------------------------------------------------
+// waveform coefficients of the potential for a run of steps
+// ---------------------------------------------------------------------------
+__global__ void coef_kernel(PotDev p, TimeDev T, int count, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count * CO_COUNT) return;
+  const int j = i / CO_COUNT, w = i % CO_COUNT;
+  out[i] = wave_value(p.w[w], step_time(T, j, T.half));
+}
+
+hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, double *out, hipStream_t s) {
+  const int n = count * CO_COUNT;
+  hipLaunchKernelGGL(coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, T, count, out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -141,15 +162,15 @@ hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s) {
 template <class R>
 __global__ void gaussian_kernel(void *out, GridDev g, const cx<double> *f0, const cx<double> *f1,
                                 const cx<double> *f2, int64_t total) {
-  using S = typename storage<R>::type;
-  S *psi = (S *)out;
+  using T = typename storage<R>::type;
+  T *psi = (T *)out;
   const int m1 = (1 << g.lg[1]) - 1, m2 = (1 << g.lg[2]) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int i2 = (int)(i & m2), i1 = (int)((i >> g.lg[2]) & m1);
     const int64_t i0 = i >> (g.lg[1] + g.lg[2]);
     const cx<double> f = cmul(cmul(f0[i0], f1[i1]), f2[i2]);
-    store_cx<R>(psi + i, cx<R>{(R)f.x, (R)f.y});
+    store_from(psi + i, f);
   }
 }
 
@@ -200,18 +221,18 @@ hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ void __launch_bounds__(kObsThreads) obs_kernel(ObsArgs a) {
-  using S = typename storage<R>::type;
+  using T = typename storage<R>::type;
   __shared__ double s_red[CO_COUNT][kObsThreads];
   __shared__ double s_coef[CO_COUNT];
   const int tid = threadIdx.x;
   if (a.with_v && tid < CO_COUNT) s_coef[tid] = wave_value(a.pot.w[tid], a.t);
   __syncthreads();
-  const S *psi = (const S *)a.psi;
+  const T *psi = (const T *)a.psi;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int m1 = (1 << a.g.lg[1]) - 1, m2 = (1 << a.g.lg[2]) - 1;
   for (int64_t i = (int64_t)blockIdx.x * kObsThreads + tid; i < a.total;
        i += (int64_t)gridDim.x * kObsThreads) {
-    const S p = psi[i];
+    const T p = psi[i];
     const double pr = p.x, pi = p.y;
     const double w = pr * pr + pi * pi;
     const int i2 = (int)(i & m2), i1 = (int)((i >> a.g.lg[2]) & m1);

@@ -24,16 +24,16 @@ constexpr int pow2_floor(int x) {
 constexpr int imin(int a, int b) { return a < b ? a : b; }
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 
-template <class R, int N, bool STRIDED, int KIND>
+template <class S, class R, int N, bool STRIDED, int KIND>
 struct pass_cfg {
-  static constexpr int ELEM = (int)sizeof(cx<R>);
+  static constexpr int ELEM = (int)sizeof(cx<R>);   // LDS element (compute type)
+  static constexpr int GELEM = (int)sizeof(cx<S>);  // HBM element (storage type)
   // 16 values per thread in FP32 (8 in FP64) halves the threads per line;
   // potential passes keep 8, whose FP64 phase evaluation needs the registers.
   static constexpr int VPT = (ELEM == 8 && N >= 16 && KIND != PK_V) ? 16 : (N < 8 ? N : 8);
   static constexpr int L = N / VPT;
   static constexpr bool EXCH = N > 8;  // more than one stage: exchanges through LDS
-  // One padding element after every 16 keeps the stage scatters spread over
-  // the banks.
+  // Padded line length (see pad16).
   static constexpr int NP = N >= 16 ? N + N / 16 : N;
   static constexpr bool TW_LDS = N <= 512;
   static constexpr int TW_BYTES = 16 * tw_count(N);
@@ -45,12 +45,12 @@ struct pass_cfg {
   static constexpr int T_THR = imax(1, 512 / L);
   // Strided lines: enough neighbouring lines that each row segment read is
   // a whole 128-byte cache line, within 512 threads.
-  static constexpr int T_MIN = STRIDED ? imin(128 / ELEM, imax(1, 512 / L)) : 1;
+  static constexpr int T_MIN = STRIDED ? imin(128 / GELEM, imax(1, 512 / L)) : 1;
   static constexpr int TILE = imin(T_LDS, imax(T_THR, T_MIN));
   static constexpr int THREADS = TILE * L;
   // Row segments shorter than a cache line: the two workgroups that share
   // each line are placed on the same XCD (see pair_blocks).
-  static constexpr bool PAIR = STRIDED && TILE * ELEM < 128;
+  static constexpr bool PAIR = STRIDED && TILE * GELEM < 128;
   static_assert(THREADS <= 1024, "workgroup too large");
   // Line data; a PK_V pass also stages its per-axis phase table here while
   // the line data is in registers.
@@ -91,18 +91,17 @@ __device__ __forceinline__ double coord(const GridDev &g, int d, int i) {
   return g.lo[d] + (double)i * g.dx[d];
 }
 
-template <class R, int N, bool STRIDED, int KIND>
-__global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
-                                  (pass_cfg<R, N, STRIDED, KIND>::WAVES_EU))
+template <class S, class R, int N, bool STRIDED, int KIND>
+__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
+                                  (pass_cfg<S, R, N, STRIDED, KIND>::WAVES_EU))
     pass_kernel(PassArgs a) {
-  using C = pass_cfg<R, N, STRIDED, KIND>;
-  using S = typename storage<R>::type;
+  using C = pass_cfg<S, R, N, STRIDED, KIND>;
+  using T = typename storage<S>::type;
   constexpr int L = C::L, VPT = C::VPT, TILE = C::TILE, NT = C::THREADS;
 
   __shared__ __align__(16) unsigned char s_raw[C::DATA_BYTES > 0 ? C::DATA_BYTES : 16];
   __shared__ cx<double> s_tw[C::TW_LDS ? tw_count(N) : 1];
   __shared__ cx<double> s_ktab[KIND == PK_K ? N : 1];
-  __shared__ double s_coef[CO_COUNT];
   cx<R> *s_data = reinterpret_cast<cx<R> *>(s_raw);
 
   const int tid = threadIdx.x;
@@ -114,13 +113,13 @@ __global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
   const int lgi = a.lg_inner;
   const int64_t o = line >> lgi, c = line & (((int64_t)1 << lgi) - 1);
   const int64_t base = (o << (fft_shape<N>::lg + lgi)) + c;
-  S *psi = (S *)a.psi;
+  T *psi = (T *)a.psi;
   const uint32_t ops = a.ops;
 
   cx<R> v[VPT];
   if (valid) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = load_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi));
+    for (int u = 0; u < VPT; ++u) v[u] = load_as<R>(psi + base + ((int64_t)(t + L * u) << lgi));
   } else {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
@@ -129,8 +128,6 @@ __global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
   if constexpr (C::TW_LDS)
     for (int e = tid; e < tw_count(N); e += NT) s_tw[e] = a.tw[e];
   const cx<double> *tw = C::TW_LDS ? (const cx<double> *)s_tw : a.tw;
-  if constexpr (KIND == PK_V)
-    if (tid < CO_COUNT) s_coef[tid] = wave_value(a.pot.w[tid], time_of(a.time));
   if constexpr (KIND == PK_K) {
     for (int e = tid; e < N; e += NT) s_ktab[e] = a.ktab[a.axis][e];
     __syncthreads();
@@ -140,9 +137,9 @@ __global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
   int idx[3];
   decode_line(a.g, a.axis, o, c, idx);
 
-  auto lds = [&](int i) -> cx<R> & {
-    if constexpr (STRIDED) return s_data[(i + (i >> 4)) * TILE + tau];
-    else return s_data[tau * C::NP + i + (i >> 4)];
+  auto lds = [&](int p) -> cx<R> & {
+    if constexpr (STRIDED) return s_data[p * TILE + tau];
+    else return s_data[tau * C::NP + p];
   };
 
   if constexpr (KIND == PK_F) {
@@ -159,7 +156,7 @@ __global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
     for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_ktab[t + L * u], kl));
     line_fft<N, VPT, true>(v, t, tw, lds);
   } else {
-    __syncthreads();  // s_coef
+    const double *s_coef = a.coef;  // uniform: scalar loads
     const int ax = a.axis;
     const double vt = a.vtau;
     // phase = vt * (c + sum_d [a_d x_d + b_d x_d^2] + s V0(x)); the terms of
@@ -204,7 +201,7 @@ __global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
           const double e = 1.0 - exp(-p1 * (x - p2));
           th += cs * p0 * e * e;
         }
-        v[u] = mul_acc(v[u], expmi_taylor(th));
+        v[u] = mul_acc(v[u], expmi_wave(th));
       }
     }
     if (ops & OP_FWD) line_fft<N, VPT, false>(v, t, tw, lds);  // starts with a barrier
@@ -212,41 +209,41 @@ __global__ void __launch_bounds__((pass_cfg<R, N, STRIDED, KIND>::THREADS),
 
   if (valid) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) store_cx<R>(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
+    for (int u = 0; u < VPT; ++u) store_from(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
   }
 }
 
-template <class R, int N, bool STRIDED, int KIND>
+template <class S, class R, int N, bool STRIDED, int KIND>
 hipError_t launch_pass_t(const PassArgs &a, hipStream_t s) {
-  using C = pass_cfg<R, N, STRIDED, KIND>;
+  using C = pass_cfg<S, R, N, STRIDED, KIND>;
   const int64_t blocks = (a.n_lines + C::TILE - 1) / C::TILE;
-  hipLaunchKernelGGL((pass_kernel<R, N, STRIDED, KIND>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+  hipLaunchKernelGGL((pass_kernel<S, R, N, STRIDED, KIND>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
-template <class R, int N>
+template <class S, class R, int N>
 hipError_t launch_pass_n(const PassArgs &a, hipStream_t s) {
   const bool strided = a.lg_inner > 0;
-  if (a.ops & OP_V) return strided ? launch_pass_t<R, N, true, PK_V>(a, s) : launch_pass_t<R, N, false, PK_V>(a, s);
-  if (a.ops & OP_K) return strided ? launch_pass_t<R, N, true, PK_K>(a, s) : launch_pass_t<R, N, false, PK_K>(a, s);
-  return strided ? launch_pass_t<R, N, true, PK_F>(a, s) : launch_pass_t<R, N, false, PK_F>(a, s);
+  if (a.ops & OP_V) return strided ? launch_pass_t<S, R, N, true, PK_V>(a, s) : launch_pass_t<S, R, N, false, PK_V>(a, s);
+  if (a.ops & OP_K) return strided ? launch_pass_t<S, R, N, true, PK_K>(a, s) : launch_pass_t<S, R, N, false, PK_K>(a, s);
+  return strided ? launch_pass_t<S, R, N, true, PK_F>(a, s) : launch_pass_t<S, R, N, false, PK_F>(a, s);
 }
 
-template <class R>
+template <class S, class R>
 hipError_t dispatch_pass(int lgN, const PassArgs &a, hipStream_t s) {
   switch (lgN) {
-    case 1: return launch_pass_n<R, 2>(a, s);
-    case 2: return launch_pass_n<R, 4>(a, s);
-    case 3: return launch_pass_n<R, 8>(a, s);
-    case 4: return launch_pass_n<R, 16>(a, s);
-    case 5: return launch_pass_n<R, 32>(a, s);
-    case 6: return launch_pass_n<R, 64>(a, s);
-    case 7: return launch_pass_n<R, 128>(a, s);
-    case 8: return launch_pass_n<R, 256>(a, s);
-    case 9: return launch_pass_n<R, 512>(a, s);
-    case 10: return launch_pass_n<R, 1024>(a, s);
-    case 11: return launch_pass_n<R, 2048>(a, s);
-    case 12: return launch_pass_n<R, 4096>(a, s);
+    case 1: return launch_pass_n<S, R, 2>(a, s);
+    case 2: return launch_pass_n<S, R, 4>(a, s);
+    case 3: return launch_pass_n<S, R, 8>(a, s);
+    case 4: return launch_pass_n<S, R, 16>(a, s);
+    case 5: return launch_pass_n<S, R, 32>(a, s);
+    case 6: return launch_pass_n<S, R, 64>(a, s);
+    case 7: return launch_pass_n<S, R, 128>(a, s);
+    case 8: return launch_pass_n<S, R, 256>(a, s);
+    case 9: return launch_pass_n<S, R, 512>(a, s);
+    case 10: return launch_pass_n<S, R, 1024>(a, s);
+    case 11: return launch_pass_n<S, R, 2048>(a, s);
+    case 12: return launch_pass_n<S, R, 4096>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

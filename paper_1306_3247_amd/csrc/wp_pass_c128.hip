@@ -3,6 +3,6 @@
 
 namespace wp {
 
-hipError_t dispatch_pass_c128(int lgN, const PassArgs &a, hipStream_t s) { return dispatch_pass<double>(lgN, a, s); }
+hipError_t dispatch_pass_c128(int lgN, const PassArgs &a, hipStream_t s) { return dispatch_pass<double, double>(lgN, a, s); }
 
 }  // namespace wp

@@ -16,8 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwavepacket.so")
 
-WP_C64, WP_C128 = 1, 2
-PRECISIONS = {"c64": WP_C64, "c128": WP_C128}
+WP_C64, WP_C128, WP_C64X = 1, 2, 3
+PRECISIONS = {"c64": WP_C64, "c128": WP_C128, "c64x": WP_C64X}
 WAVE_KINDS = {"const": 0, "sin": 1, "cos": 2, "gauss_cos": 3, "sin2_cos": 4}
 V0_KINDS = {"none": 0, "softcore": 1, "morse": 2}
 ORDERS = {"vkv": 0, "kvk": 1}
@@ -249,7 +249,7 @@ class Simulation:
     def synchronize(self) -> None:
         self._check(lib.wp_synchronize(self._h), "wp_synchronize")
 
-    PASS_KINDS = ("solve1d", "axis0", "mid_fwd", "last", "mid_inv", "edge")
+    PASS_KINDS = ("solve1d", "axis0", "mid_fwd", "last", "mid_inv", "edge", "coef")
 
     def profile_propagate(self, nsteps: int) -> dict:
         """Propagate with a device-timed event pair around every kernel;

@@ -87,7 +87,7 @@ def test_invalid_grids_rejected(lib, bad):
 
 def test_invalid_precision_rejected(lib):
     d = _desc(_grid())
-    d.prec = 3
+    d.prec = 4
     rc, _ = _state_bytes(lib, d)
     assert rc == -1
 
