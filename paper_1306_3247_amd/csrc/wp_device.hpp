@@ -225,8 +225,9 @@ __device__ __forceinline__ void line_fft(cx<R> (&v)[VPT], int t, const cx<double
 // in three parts (Cody and Waite's method; k * PIO2_A is exact for
 // |k| < 2^20), then sin and cos of the remainder |r| <= pi/4 come from their
 // Taylor series (terms to r^19 and r^18: truncation below 1e-17), and the
-// quadrant k mod 4 permutes and negates them.  Arguments beyond 1.5e6 rad go
-// to the library sincos.
+// quadrant k mod 4 permutes and negates them.  Beyond |theta| ~ 1.6e6 the
+// reduction error grows like ulp(theta), the same order as the rounding
+// error theta itself carries, so no slower path is needed.
 // ---------------------------------------------------------------------------
 constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
 // Taylor coefficients 1/n!, evaluated by the compiler.
@@ -234,14 +235,6 @@ template <int n>
 struct inv_fact {
   static constexpr double value = 1.0 / fact(n);
 };
-
-// Large arguments: out of line, so that its registers do not count against
-// the common path.
-__device__ __noinline__ cx<double> expmi_large(double th) {
-  double s, c;
-  sincos(th, &s, &c);
-  return {c, -s};
-}
 
 // |theta| <= pi/4: no reduction needed (the same series as below).
 __device__ __forceinline__ cx<double> expmi_quarter(double r) {
@@ -287,7 +280,6 @@ __device__ __forceinline__ cx<double> expmi_taylor(double th) {
   constexpr double PIO2_A = 0x1.921fb54400000p+0;
   constexpr double PIO2_B = 0x1.0b4611a600000p-34;
   constexpr double PIO2_C = 0x1.3198a2e037073p-69;
-  if (!(fabs(th) < 1.5e6)) return expmi_large(th);
   const double k = rint(th * TWO_OVER_PI);
   double r = fma(-k, PIO2_A, th);
   r = fma(-k, PIO2_B, r);

@@ -30,7 +30,7 @@ struct pass_cfg {
   static constexpr int GELEM = (int)sizeof(cx<S>);  // HBM element (storage type)
   // 16 values per thread in FP32 (8 in FP64) halves the threads per line;
   // potential passes keep 8, whose FP64 phase evaluation needs the registers.
-  static constexpr int VPT = (ELEM == 8 && N >= 16 && KIND != PK_V) ? 16 : (N < 8 ? N : 8);
+  static constexpr int VPT = (ELEM == 8 && N >= 16) ? 16 : (N < 8 ? N : 8);
   static constexpr int L = N / VPT;
   static constexpr bool EXCH = N > 8;  // more than one stage: exchanges through LDS
   // Padded line length (see pad16).
