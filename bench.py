@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "site-steps/s at 3D 512³ FP32 vs FP64; p50/p99 latency of served solves"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("paper_1306_3247_amd/csrc/wp_kernels.hip", "paper_1306_3247_amd/csrc/wp_device.hpp",
-                  "paper_1306_3247_amd/csrc/wp_internal.hpp")
+                  "paper_1306_3247_amd/csrc/wp_internal.hpp", "paper_1306_3247_amd/csrc/wp_pass.hpp",
+                  "paper_1306_3247_amd/csrc/wp_pass_c64.hip")
 
 
 def kernel_hash() -> str:

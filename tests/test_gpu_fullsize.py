@@ -1,0 +1,126 @@
+"""GPU path at the full workload sizes, in the launch configuration bench.py
+times.  Where the oracle cannot run the whole length, these check element-wise
+parity for a few steps and properties that hold at any size for the rest:
+norm, reversibility, the classical trajectory of <x> for quadratic
+potentials, and the FP32 state against the (oracle-pinned) FP64 state after
+the full step count."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1306_3247_amd import sim
+
+    return sim
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1306_3247_amd import workloads
+
+    return workloads
+
+
+def test_softcore_512_two_steps_elementwise(S, W, oracle_mod):
+    """512^3 soft-core: 2 steps from t0 = 9.5 (inside the pulse), every point."""
+    prob = W.softcore_3d(n=512, steps=2, precision="c128")
+    prob.t0 = 9.5
+    s = S.from_problem(prob)
+    s.propagate(2)
+    got = s.get_state("c128")
+    s.close()
+    psi0 = oracle_mod.gaussian(prob.grid, prob.init.center, prob.init.sigma, prob.init.k)
+    ref = oracle_mod.propagate(prob.grid, prob.pot, psi0, 2, t0=9.5)
+    del psi0
+    assert rel_l2(got, ref) <= 1e-10
+
+
+def test_softcore_512_full_length_fp32_vs_fp64(S, W):
+    """The FP32 state after the stated 2000 steps against the FP64 state
+    (FP64 pinned to the oracle above and at smaller sizes): rel-L2 <= 1e-4,
+    norm drift <= 1e-5."""
+    import torch
+
+    prob = W.softcore_3d(n=512, steps=2000)
+    a = S.from_problem(prob, precision="c64")
+    b = S.from_problem(prob, precision="c128")
+    for s in (a, b):
+        s.propagate(2000)
+        s.synchronize()
+    x = torch.view_as_real(a.buffer.view(torch.complex64)).double()
+    y = torch.view_as_real(b.buffer.view(torch.complex128))
+    rel = float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
+    n32, n64 = a.observables(1)["norm"], b.observables(1)["norm"]
+    print(f"512^3 x 2000: rel_l2(f32, f64) = {rel:.3e}, norm drift f32 {abs(n32 - 1):.3e}, f64 {abs(n64 - 1):.3e}")
+    a.close()
+    b.close()
+    assert rel <= 1e-4
+    assert abs(n32 - 1.0) <= 1e-5
+    assert abs(n64 - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_softcore_512_reversible(S, W, precision):
+    """50 steps forward from t0 = 9, then 50 steps with -dt from the reached
+    time, return to the start (the trapezoid sampling makes the backward step
+    the exact inverse)."""
+    prob = W.softcore_3d(n=512, steps=50, precision=precision)
+    prob.t0 = 9.0
+    f = S.from_problem(prob)
+    start = f.get_state("c128")
+    f.propagate(50)
+    t, _ = f.time()
+    mid = f.get_state("c128")
+    f.close()
+    back = W.softcore_3d(n=512, steps=50, precision=precision)
+    back.grid.dt = -prob.grid.dt
+    g = S.Simulation(back.grid, back.pot, precision)
+    g.set_state(mid, t0=t)
+    del mid
+    g.propagate(50)
+    end = g.get_state("c128")
+    g.close()
+    assert rel_l2(end, start) <= (1e-12 if precision == "c128" else 1e-5)
+
+
+def test_modulated_trap_1024_mean_position_classical(S, W):
+    """Full 2D workload (1024^2, 2000 steps, FP64): for a quadratic potential
+    the mean position follows the classical kick-drift-kick trajectory."""
+    prob = W.modulated_trap_2d()
+    s = S.from_problem(prob)
+    x, p = np.array([3.0, -2.0]), np.array([0.0, 1.0])
+    dt = prob.grid.dt
+    force = lambda q, t: -np.array([(1 + 0.3 * math.cos(2 * t)) * q[0], (1 - 0.3 * math.cos(2 * t)) * q[1]])
+    for n in range(2000):
+        p = p + 0.5 * dt * force(x, n * dt)
+        x = x + dt * p
+        p = p + 0.5 * dt * force(x, (n + 1) * dt)
+    s.propagate(2000)
+    o = s.observables()
+    s.close()
+    assert abs(o["norm"] - 1.0) <= 1e-12
+    assert abs(o["x"] - x[0]) <= 1e-9 and abs(o["y"] - x[1]) <= 1e-9
+
+
+def test_modulated_trap_1024_fp32_parity_with_fp64(S, W):
+    """Full 2D workload: the FP32 state within 1e-4 of the FP64 state, FP32
+    norm drift within 1e-5."""
+    prob = W.modulated_trap_2d()
+    ref = S.from_problem(prob, precision="c128")
+    ref.propagate(2000)
+    r = ref.get_state("c128")
+    ref.close()
+    s = S.from_problem(prob, precision="c64")
+    s.propagate(2000)
+    g = s.get_state("c128")
+    n = s.observables(1)["norm"]
+    s.close()
+    assert rel_l2(g, r) <= 1e-4
+    assert abs(n - 1.0) <= 1e-5
