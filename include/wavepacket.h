@@ -219,6 +219,42 @@ enum {
  * in 1..100000 (WP_EINVAL otherwise). */
 wp_status wp_profile_propagate(wp_sim *sim, uint64_t nsteps, double *ms, uint64_t *count);
 
+/* ---- batches: many independent solves advanced together -------------- */
+
+typedef struct wp_batch wp_batch;
+
+/* Group `count` existing handles so that wp_batch_propagate advances all of
+ * them with shared launches: every pass of a step is one launch per class of
+ * solves with the same precision, line length and layout, each workgroup
+ * taking one tile of one solve (the per-solve work of Algorithm 1, many
+ * solves at once).  Solves may differ in size, dimension, potential,
+ * precision, dt and start time; all must use WP_ORDER_VKV and be on the
+ * current device.  The batch refers to the handles (it does not own them):
+ * they must outlive it, and while it exists they should be advanced only
+ * through it.  Work is ordered on `stream` (hipStream_t or NULL).  Each
+ * member's result equals its own wp_propagate result (same kernels, same
+ * reduction order).  Errors: WP_EINVAL (count 0, NULL, a member in K-V-K
+ * order), WP_ENOMEM, WP_EDEVICE. */
+wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_batch **out);
+
+/* Capture runs of k steady steps (1 <= k <= 64) of the 2D/3D members in a
+ * HIP graph and replay it; k = 0 launches directly.  Default 0.  The graph
+ * refreshes the waveform values from device step counters, so replays need
+ * no host updates.  Results do not depend on k. */
+wp_status wp_batch_set_graph_steps(wp_batch *b, uint32_t k);
+
+/* Advance every member by nsteps (asynchronous on the batch's stream).  Each
+ * member's state, step counter and time advance exactly as with
+ * wp_propagate(member, nsteps), bit for bit. */
+wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps);
+
+/* Release the batch's own device buffers and graphs (members untouched).
+ * Waits for the batch's stream. */
+wp_status wp_batch_destroy(wp_batch *b);
+
+/* Description of the last error on the batch ("" when none). */
+const char *wp_batch_last_error(const wp_batch *b);
+
 /* Current time t0 + steps*dt and step counter. */
 wp_status wp_get_time(wp_sim *sim, double *t, uint64_t *step);
 

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -697,6 +699,335 @@ wp_status wp_synchronize(wp_sim *s) {
   (void)hipSetDevice(s->device);
   hipError_t e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "synchronize");
+  return WP_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// batches
+// ===========================================================================
+
+namespace {
+
+// Argument-block variants per solve (index = solve * kVariants + variant).
+enum : int { V_FIRST = 0, V_STEADY = 1, V_LAST = 2, K_LAST = 3, F_FWD = 4, F_INV = 5, kVariants = 6 };
+// Position of a pass group within a step.
+enum : int { SLOT_FFWD = 0, SLOT_K = 1, SLOT_FINV = 2, SLOT_V = 3 };
+constexpr int kMaxSeqSteps = 64;  // steps per launch sequence (graph or direct)
+
+struct PassGroup {
+  int slot, prec, lgN, kind;
+  bool strided;
+  uint32_t item_off, nblocks;
+};
+struct Group1D {
+  int prec, lgN;
+  uint32_t off, count;
+};
+
+}  // namespace
+
+struct wp_batch {
+  std::vector<wp_sim *> sims;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int rows = kMaxSeqSteps + 1;
+  uint32_t graph_steps = 0;
+  wp::PassArgs *d_args = nullptr;
+  wp::BatchItem *d_items = nullptr;
+  wp::Solve1DArgs *d_args1d = nullptr;
+  wp::PotDev *d_pots = nullptr;
+  double *d_t0 = nullptr, *d_dt = nullptr, *d_coef = nullptr;
+  int64_t *d_step = nullptr;
+  std::vector<PassGroup> groups;
+  std::vector<Group1D> groups1d;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t exec_steps = 0;
+  // Graphs are captured and replayed on a stream of the batch's own (the
+  // caller's may be the legacy default stream, which cannot be captured),
+  // ordered after and before the caller's work by events.
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::string err;
+};
+
+namespace {
+
+void batch_release(wp_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (void *p : {(void *)b->d_args, (void *)b->d_items, (void *)b->d_args1d, (void *)b->d_pots, (void *)b->d_t0,
+                  (void *)b->d_dt, (void *)b->d_coef, (void *)b->d_step})
+    if (p) (void)hipFree(p);
+}
+
+wp_status bfail(wp_batch *b, wp_status code, const std::string &msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+// Launch every pass group of one slot of a step.
+hipError_t run_slot(wp_batch *b, hipStream_t st, int slot, int var, int row) {
+  for (const PassGroup &g : b->groups) {
+    if (g.slot != slot) continue;
+    wp::BatchLaunch L{};
+    L.args = b->d_args;
+    L.items = b->d_items + g.item_off;
+    L.nblocks = (int)g.nblocks;
+    L.nvar = kVariants;
+    L.var = var;
+    L.row = row;
+    L.lgN = g.lgN;
+    L.strided = g.strided;
+    L.kind = g.kind;
+    hipError_t r = wp::launch_batch_pass(g.prec, L, st);
+    if (r != hipSuccess) return r;
+  }
+  return hipSuccess;
+}
+
+hipError_t refresh_coef(wp_batch *b, hipStream_t st, int rows) {
+  return wp::launch_coefficients_batch(b->d_pots, b->d_t0, b->d_dt, b->d_step, 0.0, (int)b->sims.size(), rows,
+                                       b->rows, b->d_coef, st);
+}
+
+// k steady steps of the 2D/3D members (the middle passes of the step, then
+// the merged full potential step and the forward transform of the first
+// axis), then the device step counters advance by k.  Only kernel launches:
+// this is what a graph captures.
+hipError_t steady_steps(wp_batch *b, hipStream_t st, int k) {
+  hipError_t e = refresh_coef(b, st, k + 1);
+  for (int j = 0; j < k && e == hipSuccess; ++j) {
+    e = run_slot(b, st, SLOT_FFWD, F_FWD, 0);
+    if (e == hipSuccess) e = run_slot(b, st, SLOT_K, K_LAST, 0);
+    if (e == hipSuccess) e = run_slot(b, st, SLOT_FINV, F_INV, 0);
+    if (e == hipSuccess) e = run_slot(b, st, SLOT_V, V_STEADY, j + 1);
+  }
+  if (e == hipSuccess) e = wp::launch_step_advance(b->d_step, (int)b->sims.size(), k, st);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wp_batch_last_error(const wp_batch *b) { return b ? b->err.c_str() : "NULL batch"; }
+
+wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_batch **out) {
+  if (!out) return WP_EINVAL;
+  *out = nullptr;
+  if (!sims || count == 0) return WP_EINVAL;
+  for (uint32_t i = 0; i < count; ++i)
+    if (!sims[i] || sims[i]->order != WP_ORDER_VKV) return WP_EINVAL;
+  wp_batch *b = new (std::nothrow) wp_batch();
+  if (!b) return WP_ENOMEM;
+  b->sims.assign(sims, sims + count);
+  b->stream = (hipStream_t)stream;
+  hipError_t e = hipGetDevice(&b->device);
+  for (uint32_t i = 0; i < count && e == hipSuccess; ++i) e = ensure_state(b->sims[i]);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  // Per-solve host descriptors.
+  std::vector<wp::PassArgs> args((size_t)count * kVariants);
+  std::vector<wp::PotDev> pots(count);
+  std::vector<double> t0(count), dt(count);
+  std::vector<int64_t> steps(count);
+  std::vector<wp::BatchItem> items;
+  std::vector<wp::Solve1DArgs> a1d;
+  // group key -> members
+  struct Key {
+    int slot, prec, lgN, kind;
+    bool strided;
+    bool operator<(const Key &o) const {
+      return std::tie(slot, prec, lgN, kind, strided) < std::tie(o.slot, o.prec, o.lgN, o.kind, o.strided);
+    }
+  };
+  std::map<Key, std::vector<std::pair<int, int64_t>>> members;  // (solve, tiles)
+  std::map<std::pair<int, int>, std::vector<int>> members1d;    // (prec, lgN) -> solves
+  if (e == hipSuccess) {
+    e = hipMalloc((void **)&b->d_coef, sizeof(double) * wp::CO_COUNT * (size_t)b->rows * count);
+  }
+  for (uint32_t i = 0; i < count && e == hipSuccess; ++i) {
+    wp_sim *s = b->sims[i];
+    pots[i] = s->pd;
+    t0[i] = s->t0;
+    dt[i] = s->g.dt;
+    steps[i] = (int64_t)s->step;
+    if (s->g.ndim == 1) {
+      members1d[{s->prec, s->lg[0]}].push_back((int)i);
+      continue;
+    }
+    const double tau_half = 0.5 * s->g.dt / s->g.hbar, tau_full = s->g.dt / s->g.hbar;
+    const double *coef = b->d_coef + (size_t)i * b->rows * wp::CO_COUNT;
+    const int last = s->g.ndim - 1;
+    wp::PassArgs *A = &args[(size_t)i * kVariants];
+    A[V_FIRST] = pass_args(s, 0, wp::OP_V | wp::OP_FWD);
+    A[V_FIRST].vtau = tau_half;
+    A[V_STEADY] = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | wp::OP_FWD);
+    A[V_STEADY].vtau = tau_full;
+    A[V_LAST] = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V);
+    A[V_LAST].vtau = tau_half;
+    for (int v : {V_FIRST, V_STEADY, V_LAST}) A[v].coef = coef;
+    A[K_LAST] = pass_args(s, last, wp::OP_FWD | wp::OP_K | wp::OP_POST_INV);
+    if (s->g.ndim == 3) {
+      A[F_FWD] = pass_args(s, 1, wp::OP_FWD);
+      A[F_INV] = pass_args(s, 1, wp::OP_PRE_INV);
+    }
+    auto add = [&](int slot, int axis, int kind) {
+      const wp::PassArgs &pa = A[slot == SLOT_V ? V_FIRST : slot == SLOT_K ? K_LAST : slot == SLOT_FFWD ? F_FWD : F_INV];
+      const bool strided = pa.lg_inner > 0;
+      const int tile = wp::pass_tile(s->prec, s->lg[axis], strided, kind);
+      const int64_t tiles = (pa.n_lines + tile - 1) / tile;
+      members[{slot, s->prec, s->lg[axis], kind, strided}].push_back({(int)i, tiles});
+    };
+    add(SLOT_V, 0, 1);
+    add(SLOT_K, last, 2);
+    if (s->g.ndim == 3) {
+      add(SLOT_FFWD, 1, 0);
+      add(SLOT_FINV, 1, 0);
+    }
+  }
+  if (e == hipSuccess) {
+    for (auto &kv : members) {
+      PassGroup g{kv.first.slot, kv.first.prec, kv.first.lgN, kv.first.kind, kv.first.strided,
+                  (uint32_t)items.size(), 0};
+      for (auto &m : kv.second)
+        for (int64_t t = 0; t < m.second; ++t) items.push_back({m.first, (int32_t)t});
+      g.nblocks = (uint32_t)(items.size() - g.item_off);
+      b->groups.push_back(g);
+    }
+    for (auto &kv : members1d) {
+      Group1D g{kv.first.first, kv.first.second, (uint32_t)a1d.size(), (uint32_t)kv.second.size()};
+      for (int i : kv.second) {
+        wp_sim *s = b->sims[i];
+        wp::Solve1DArgs a{};
+        a.psi = s->psi;
+        a.g = s->gd;
+        a.nsteps = 0;
+        a.time.t0 = s->t0;
+        a.time.dt = s->g.dt;
+        a.time.step = 0;
+        a.time.half = 0.0;
+        a.vtau_half = 0.5 * s->g.dt / s->g.hbar;
+        a.vtau_full = s->g.dt / s->g.hbar;
+        a.order = WP_ORDER_VKV;
+        a.pot = s->pd;
+        a.kfull = s->d_kfull;
+        a.khalf = s->d_khalf;
+        a.tw = s->d_tw[0];
+        a1d.push_back(a);
+      }
+      b->groups1d.push_back(g);
+    }
+  }
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_step, sizeof(int64_t) * count);
+  // The 1D argument blocks read their step from the device counters.
+  for (size_t j = 0, gi = 0; e == hipSuccess && gi < b->groups1d.size(); ++gi)
+    for (int i : members1d[{b->groups1d[gi].prec, b->groups1d[gi].lgN}]) a1d[j++].time.step_dev = b->d_step + i;
+  if (e == hipSuccess) e = upload(&b->d_args, args);
+  if (e == hipSuccess && !items.empty()) e = upload(&b->d_items, items);
+  if (e == hipSuccess && !a1d.empty()) e = upload(&b->d_args1d, a1d);
+  if (e == hipSuccess) e = upload(&b->d_pots, pots);
+  if (e == hipSuccess) e = upload(&b->d_t0, t0);
+  if (e == hipSuccess) e = upload(&b->d_dt, dt);
+  if (e == hipSuccess) e = hipMemcpy(b->d_step, steps.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    batch_release(b);
+    delete b;
+    return e == hipErrorOutOfMemory ? WP_ENOMEM : WP_EDEVICE;
+  }
+  *out = b;
+  return WP_OK;
+}
+
+wp_status wp_batch_set_graph_steps(wp_batch *b, uint32_t k) {
+  if (!b) return WP_EINVAL;
+  if (k > (uint32_t)kMaxSeqSteps) return bfail(b, WP_EINVAL, "graph steps must be in 0..64");
+  b->graph_steps = k;
+  return WP_OK;
+}
+
+wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps) {
+  if (!b) return WP_EINVAL;
+  if (nsteps == 0) return WP_OK;
+  (void)hipSetDevice(b->device);
+  const int count = (int)b->sims.size();
+  // The members' host counters are authoritative: refresh the device copy.
+  std::vector<int64_t> steps(count);
+  for (int i = 0; i < count; ++i) steps[i] = (int64_t)b->sims[i]->step;
+  hipError_t e = hipMemcpyAsync(b->d_step, steps.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  // 1D members: all steps in one launch per line-length class.
+  for (const Group1D &g : b->groups1d) {
+    if (e != hipSuccess) break;
+    e = wp::launch_solve1d_batch(g.prec, g.lgN, b->d_args1d + g.off, (int)g.count, (int64_t)nsteps, b->stream);
+  }
+  // 2D/3D members: open (potential half step at t_n and forward transform of
+  // the first axis), nsteps-1 steady steps, and a final step closing with the
+  // potential half step: the same sequence as wp_propagate, however the
+  // steady steps are split between graph replays and direct launches.
+  if (e == hipSuccess && !b->groups.empty()) {
+    e = refresh_coef(b, b->stream, 1);
+    if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_V, V_FIRST, 0);
+    uint64_t left = nsteps - 1;
+    const uint32_t k = b->graph_steps;
+    if (e == hipSuccess && k > 0 && left >= k) {
+      if (!b->cap_stream) {
+        e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+      }
+      if (e == hipSuccess && (!b->exec || b->exec_steps != k)) {
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          hipError_t ce = steady_steps(b, b->cap_stream, (int)k);
+          e = hipStreamEndCapture(b->cap_stream, &b->graph);
+          if (ce != hipSuccess) e = ce;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) b->exec_steps = k;
+      }
+      if (e == hipSuccess) e = hipEventRecord(b->ev_in, b->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->cap_stream, b->ev_in, 0);
+      while (e == hipSuccess && left >= k) {
+        e = hipGraphLaunch(b->exec, b->cap_stream);
+        left -= k;
+      }
+      if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->cap_stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out, 0);
+    }
+    while (e == hipSuccess && left > 0) {
+      const int kk = (int)(left < (uint64_t)kMaxSeqSteps ? left : (uint64_t)kMaxSeqSteps);
+      e = steady_steps(b, b->stream, kk);
+      left -= (uint64_t)kk;
+    }
+    // final step
+    if (e == hipSuccess) e = refresh_coef(b, b->stream, 2);
+    if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_FFWD, F_FWD, 0);
+    if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_K, K_LAST, 0);
+    if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_FINV, F_INV, 0);
+    if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_V, V_LAST, 1);
+  }
+  if (e != hipSuccess) return bfail(b, WP_EDEVICE, std::string("batch_propagate: ") + hipGetErrorString(e));
+  for (wp_sim *s : b->sims) s->step += nsteps;
+  b->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_batch_destroy(wp_batch *b) {
+  if (!b) return WP_EINVAL;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  batch_release(b);
+  delete b;
   return WP_OK;
 }
 

@@ -77,6 +77,24 @@ struct ObsArgs {
   double *partials;        // [blocks][8]
 };
 
+// One workgroup of a batched pass: tile `tile` of solve `solve`.
+struct BatchItem {
+  int32_t solve;
+  int32_t tile;
+};
+
+// A batched pass launch: `nblocks` workgroups described by `items`, all of
+// the same precision, line length 2^lgN, layout and kind.
+struct BatchLaunch {
+  const PassArgs *args;
+  const BatchItem *items;
+  int nblocks;
+  int nvar, var, row;
+  int lgN;
+  bool strided;
+  int kind;  // 0 FFT only, 1 potential, 2 kinetic
+};
+
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s);
 hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s);
@@ -97,5 +115,17 @@ constexpr int kObsThreads = 256;
 constexpr int kCoefChunk = 1024;  // steps per coefficient table
 
 bool pass_supported(int prec, int lgN);
+hipError_t launch_batch_pass(int prec, const BatchLaunch &b, hipStream_t s);
+int pass_tile(int prec, int lgN, bool strided, int kind);
+// 1D solves in one launch, one workgroup each (all of line length 2^lgN).
+hipError_t launch_solve1d_batch(int prec, int lgN, const Solve1DArgs *args, int count, int64_t nsteps,
+                                hipStream_t s);
+// step[i] += k for i < count.
+hipError_t launch_step_advance(int64_t *step, int count, int64_t k, hipStream_t s);
+// Waveform values for many solves: out[(i*stride + j)*CO_COUNT + w], j < rows,
+// is waveform w of solve i at the time of step step_dev[i] + j (plus half).
+hipError_t launch_coefficients_batch(const PotDev *pots, const double *t0, const double *dt,
+                                     const int64_t *step_dev, double half, int count, int rows, int stride,
+                                     double *out, hipStream_t s);
 
 }  // namespace wp

@@ -12,6 +12,25 @@ namespace wp {
 hipError_t dispatch_pass_c64(int lgN, const PassArgs &a, hipStream_t s);
 hipError_t dispatch_pass_c64x(int lgN, const PassArgs &a, hipStream_t s);
 hipError_t dispatch_pass_c128(int lgN, const PassArgs &a, hipStream_t s);
+hipError_t dispatch_batch_c64(const BatchLaunch &b, hipStream_t s);
+hipError_t dispatch_batch_c64x(const BatchLaunch &b, hipStream_t s);
+hipError_t dispatch_batch_c128(const BatchLaunch &b, hipStream_t s);
+int pass_tile_c64(int lgN, bool strided, int kind);
+int pass_tile_c64x(int lgN, bool strided, int kind);
+int pass_tile_c128(int lgN, bool strided, int kind);
+
+hipError_t launch_batch_pass(int prec, const BatchLaunch &b, hipStream_t s) {
+  if (!pass_supported(prec, b.lgN) || b.nblocks <= 0) return hipErrorInvalidValue;
+  if (prec == 2) return dispatch_batch_c128(b, s);
+  if (prec == 3) return dispatch_batch_c64x(b, s);
+  return dispatch_batch_c64(b, s);
+}
+
+int pass_tile(int prec, int lgN, bool strided, int kind) {
+  if (prec == 2) return pass_tile_c128(lgN, strided, kind);
+  if (prec == 3) return pass_tile_c64x(lgN, strided, kind);
+  return pass_tile_c64(lgN, strided, kind);
+}
 
 bool pass_supported(int prec, int lgN) { return prec >= 1 && prec <= 3 && lgN >= 1 && lgN <= 12; }
 
@@ -34,7 +53,7 @@ __device__ __forceinline__ double step_time(const TimeDev &T, int64_t s, double 
 }
 
 template <class S, class R, int N>
-__global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a) {
+__device__ __forceinline__ void solve1d_body(const Solve1DArgs &a) {
   using T = typename storage<S>::type;
   constexpr int L = fft_shape<N>::L, VPT = fft_shape<N>::VPT;
   static_assert(VPT <= 8, "one thread holds at most 8 values here");
@@ -108,36 +127,73 @@ __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a)
 }
 
 template <class S, class R, int N>
-static hipError_t launch_solve1d_t(const Solve1DArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((solve1d_kernel<S, R, N>), dim3(1), dim3(fft_shape<N>::L), 0, s, a);
+__global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a) {
+  solve1d_body<S, R, N>(a);
+}
+
+// One workgroup per solve.
+template <class S, class R, int N>
+__global__ void __launch_bounds__(fft_shape<N>::L) solve1d_batch_kernel(const Solve1DArgs *args, int64_t nsteps) {
+  Solve1DArgs a = args[blockIdx.x];
+  a.nsteps = nsteps;
+  solve1d_body<S, R, N>(a);
+}
+
+template <class S, class R, int N>
+static hipError_t launch_solve1d_t(const Solve1DArgs &a, hipStream_t s, const Solve1DArgs *batch, int count) {
+  if (batch)
+    hipLaunchKernelGGL((solve1d_batch_kernel<S, R, N>), dim3(count), dim3(fft_shape<N>::L), 0, s, batch, a.nsteps);
+  else
+    hipLaunchKernelGGL((solve1d_kernel<S, R, N>), dim3(1), dim3(fft_shape<N>::L), 0, s, a);
   return hipGetLastError();
 }
 
 template <class S, class R>
-static hipError_t dispatch_solve1d(int lgN, const Solve1DArgs &a, hipStream_t s) {
+static hipError_t dispatch_solve1d(int lgN, const Solve1DArgs &a, hipStream_t s, const Solve1DArgs *batch,
+                                   int count) {
   switch (lgN) {
-    case 1: return launch_solve1d_t<S, R, 2>(a, s);
-    case 2: return launch_solve1d_t<S, R, 4>(a, s);
-    case 3: return launch_solve1d_t<S, R, 8>(a, s);
-    case 4: return launch_solve1d_t<S, R, 16>(a, s);
-    case 5: return launch_solve1d_t<S, R, 32>(a, s);
-    case 6: return launch_solve1d_t<S, R, 64>(a, s);
-    case 7: return launch_solve1d_t<S, R, 128>(a, s);
-    case 8: return launch_solve1d_t<S, R, 256>(a, s);
-    case 9: return launch_solve1d_t<S, R, 512>(a, s);
-    case 10: return launch_solve1d_t<S, R, 1024>(a, s);
-    case 11: return launch_solve1d_t<S, R, 2048>(a, s);
-    case 12: return launch_solve1d_t<S, R, 4096>(a, s);
-    case 13: return launch_solve1d_t<S, R, 8192>(a, s);
+    case 1: return launch_solve1d_t<S, R, 2>(a, s, batch, count);
+    case 2: return launch_solve1d_t<S, R, 4>(a, s, batch, count);
+    case 3: return launch_solve1d_t<S, R, 8>(a, s, batch, count);
+    case 4: return launch_solve1d_t<S, R, 16>(a, s, batch, count);
+    case 5: return launch_solve1d_t<S, R, 32>(a, s, batch, count);
+    case 6: return launch_solve1d_t<S, R, 64>(a, s, batch, count);
+    case 7: return launch_solve1d_t<S, R, 128>(a, s, batch, count);
+    case 8: return launch_solve1d_t<S, R, 256>(a, s, batch, count);
+    case 9: return launch_solve1d_t<S, R, 512>(a, s, batch, count);
+    case 10: return launch_solve1d_t<S, R, 1024>(a, s, batch, count);
+    case 11: return launch_solve1d_t<S, R, 2048>(a, s, batch, count);
+    case 12: return launch_solve1d_t<S, R, 4096>(a, s, batch, count);
+    case 13: return launch_solve1d_t<S, R, 8192>(a, s, batch, count);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s) {
   const int lgN = a.g.lg[0];
-  if (prec == 2) return dispatch_solve1d<double, double>(lgN, a, s);
-  if (prec == 3) return dispatch_solve1d<float, double>(lgN, a, s);
-  return dispatch_solve1d<float, float>(lgN, a, s);
+  if (prec == 2) return dispatch_solve1d<double, double>(lgN, a, s, nullptr, 1);
+  if (prec == 3) return dispatch_solve1d<float, double>(lgN, a, s, nullptr, 1);
+  return dispatch_solve1d<float, float>(lgN, a, s, nullptr, 1);
+}
+
+hipError_t launch_solve1d_batch(int prec, int lgN, const Solve1DArgs *args, int count, int64_t nsteps,
+                                hipStream_t s) {
+  if (count <= 0) return hipErrorInvalidValue;
+  Solve1DArgs unused{};
+  unused.nsteps = nsteps;
+  if (prec == 2) return dispatch_solve1d<double, double>(lgN, unused, s, args, count);
+  if (prec == 3) return dispatch_solve1d<float, double>(lgN, unused, s, args, count);
+  return dispatch_solve1d<float, float>(lgN, unused, s, args, count);
+}
+
+__global__ void step_advance_kernel(int64_t *step, int count, int64_t k) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) step[i] += k;
+}
+
+hipError_t launch_step_advance(int64_t *step, int count, int64_t k, hipStream_t s) {
+  hipLaunchKernelGGL(step_advance_kernel, dim3((count + 255) / 256), dim3(256), 0, s, step, count, k);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -153,6 +209,30 @@ __global__ void coef_kernel(PotDev p, TimeDev T, int count, double *out) {
 hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, double *out, hipStream_t s) {
   const int n = count * CO_COUNT;
   hipLaunchKernelGGL(coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, T, count, out);
+  return hipGetLastError();
+}
+
+// Many solves at once; the step of solve i is read from step_dev[i] on the
+// device, so the launch can be replayed from a graph.
+__global__ void coef_batch_kernel(const PotDev *pots, const double *t0, const double *dt, const int64_t *step_dev,
+                                  double half, int count, int rows, int stride, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)count * rows * CO_COUNT) return;
+  const int w = (int)(i % CO_COUNT);
+  const int64_t jr = i / CO_COUNT;
+  const int j = (int)(jr % rows);
+  const int m = (int)(jr / rows);
+  const double t = t0[m] + ((double)(step_dev[m] + j) + half) * dt[m];
+  out[((int64_t)m * stride + j) * CO_COUNT + w] = wave_value(pots[m].w[w], t);
+}
+
+hipError_t launch_coefficients_batch(const PotDev *pots, const double *t0, const double *dt,
+                                     const int64_t *step_dev, double half, int count, int rows, int stride,
+                                     double *out, hipStream_t s) {
+  if (rows > stride) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)count * rows * CO_COUNT;
+  hipLaunchKernelGGL(coef_batch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pots, t0, dt, step_dev,
+                     half, count, rows, stride, out);
   return hipGetLastError();
 }
 

@@ -10,6 +10,8 @@
 // more workgroups fit in a CU's 160 KiB of LDS, letting one workgroup load
 // while another computes.
 #pragma once
+#include <type_traits>
+
 #include "wp_internal.hpp"
 
 namespace wp {
@@ -91,10 +93,10 @@ __device__ __forceinline__ double coord(const GridDev &g, int d, int i) {
   return g.lo[d] + (double)i * g.dx[d];
 }
 
+// The work of one workgroup: tile `blk` of the lines described by `a`;
+// `coef` holds the CO_COUNT waveform values at the pass's time (kind V).
 template <class S, class R, int N, bool STRIDED, int KIND>
-__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
-                                  (pass_cfg<S, R, N, STRIDED, KIND>::WAVES_EU))
-    pass_kernel(PassArgs a) {
+__device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef, unsigned blk) {
   using C = pass_cfg<S, R, N, STRIDED, KIND>;
   using T = typename storage<S>::type;
   constexpr int L = C::L, VPT = C::VPT, TILE = C::TILE, NT = C::THREADS;
@@ -107,7 +109,6 @@ __global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
   const int tid = threadIdx.x;
   const int tau = STRIDED ? tid % TILE : tid / L;
   const int t = STRIDED ? tid / TILE : tid % L;
-  const unsigned blk = C::PAIR ? pair_blocks(blockIdx.x, gridDim.x) : blockIdx.x;
   const int64_t line = (int64_t)blk * TILE + tau;
   const bool valid = line < a.n_lines;
   const int lgi = a.lg_inner;
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
     for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_ktab[t + L * u], kl));
     line_fft<N, VPT, true>(v, t, tw, lds);
   } else {
-    const double *s_coef = a.coef;  // uniform: scalar loads
+    const double *s_coef = coef;  // uniform: scalar loads
     const int ax = a.axis;
     const double vt = a.vtau;
     // phase = vt * (c + sum_d [a_d x_d + b_d x_d^2] + s V0(x)); the terms of
@@ -210,6 +211,87 @@ __global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
   if (valid) {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) store_from(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
+  }
+}
+
+template <class S, class R, int N, bool STRIDED, int KIND>
+__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
+                                  (pass_cfg<S, R, N, STRIDED, KIND>::WAVES_EU))
+    pass_kernel(PassArgs a) {
+  using C = pass_cfg<S, R, N, STRIDED, KIND>;
+  const unsigned blk = C::PAIR ? pair_blocks(blockIdx.x, gridDim.x) : blockIdx.x;
+  pass_body<S, R, N, STRIDED, KIND>(a, a.coef, blk);
+}
+
+// Batched: workgroup b runs tile items[b].tile of solve items[b].solve, whose
+// argument block is args[items[b].solve * nvar + var]; `row` selects the
+// waveform values of the step this launch belongs to.
+template <class S, class R, int N, bool STRIDED, int KIND>
+__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
+                                  (pass_cfg<S, R, N, STRIDED, KIND>::WAVES_EU))
+    batch_pass_kernel(const PassArgs *args, const BatchItem *items, int nvar, int var, int row) {
+  const BatchItem it = items[blockIdx.x];
+  const PassArgs a = args[it.solve * nvar + var];
+  pass_body<S, R, N, STRIDED, KIND>(a, a.coef ? a.coef + row * CO_COUNT : nullptr, (unsigned)it.tile);
+}
+
+template <class S, class R, int N, bool STRIDED, int KIND>
+hipError_t launch_batch_t(const BatchLaunch &b, hipStream_t s) {
+  using C = pass_cfg<S, R, N, STRIDED, KIND>;
+  hipLaunchKernelGGL((batch_pass_kernel<S, R, N, STRIDED, KIND>), dim3(b.nblocks), dim3(C::THREADS), 0, s,
+                     b.args, b.items, b.nvar, b.var, b.row);
+  return hipGetLastError();
+}
+
+template <class S, class R, int N>
+hipError_t launch_batch_n(const BatchLaunch &b, hipStream_t s) {
+  if (b.kind == PK_V) return b.strided ? launch_batch_t<S, R, N, true, PK_V>(b, s) : launch_batch_t<S, R, N, false, PK_V>(b, s);
+  if (b.kind == PK_K) return b.strided ? launch_batch_t<S, R, N, true, PK_K>(b, s) : launch_batch_t<S, R, N, false, PK_K>(b, s);
+  return b.strided ? launch_batch_t<S, R, N, true, PK_F>(b, s) : launch_batch_t<S, R, N, false, PK_F>(b, s);
+}
+
+template <class S, class R>
+hipError_t dispatch_batch(const BatchLaunch &b, hipStream_t s) {
+  switch (b.lgN) {
+    case 1: return launch_batch_n<S, R, 2>(b, s);
+    case 2: return launch_batch_n<S, R, 4>(b, s);
+    case 3: return launch_batch_n<S, R, 8>(b, s);
+    case 4: return launch_batch_n<S, R, 16>(b, s);
+    case 5: return launch_batch_n<S, R, 32>(b, s);
+    case 6: return launch_batch_n<S, R, 64>(b, s);
+    case 7: return launch_batch_n<S, R, 128>(b, s);
+    case 8: return launch_batch_n<S, R, 256>(b, s);
+    case 9: return launch_batch_n<S, R, 512>(b, s);
+    case 10: return launch_batch_n<S, R, 1024>(b, s);
+    case 11: return launch_batch_n<S, R, 2048>(b, s);
+    case 12: return launch_batch_n<S, R, 4096>(b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Lines per workgroup of a pass configuration (the host sizes block maps with it).
+template <class S, class R>
+int pass_tile_t(int lgN, bool strided, int kind) {
+  auto pick = [&](auto n) -> int {
+    constexpr int NN = decltype(n)::value;
+    if (kind == PK_V) return strided ? pass_cfg<S, R, NN, true, PK_V>::TILE : pass_cfg<S, R, NN, false, PK_V>::TILE;
+    if (kind == PK_K) return strided ? pass_cfg<S, R, NN, true, PK_K>::TILE : pass_cfg<S, R, NN, false, PK_K>::TILE;
+    return strided ? pass_cfg<S, R, NN, true, PK_F>::TILE : pass_cfg<S, R, NN, false, PK_F>::TILE;
+  };
+  switch (lgN) {
+    case 1: return pick(std::integral_constant<int, 2>{});
+    case 2: return pick(std::integral_constant<int, 4>{});
+    case 3: return pick(std::integral_constant<int, 8>{});
+    case 4: return pick(std::integral_constant<int, 16>{});
+    case 5: return pick(std::integral_constant<int, 32>{});
+    case 6: return pick(std::integral_constant<int, 64>{});
+    case 7: return pick(std::integral_constant<int, 128>{});
+    case 8: return pick(std::integral_constant<int, 256>{});
+    case 9: return pick(std::integral_constant<int, 512>{});
+    case 10: return pick(std::integral_constant<int, 1024>{});
+    case 11: return pick(std::integral_constant<int, 2048>{});
+    case 12: return pick(std::integral_constant<int, 4096>{});
+    default: return 0;
   }
 }
 

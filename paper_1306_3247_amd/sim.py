@@ -88,6 +88,10 @@ def _load() -> C.CDLL:
         "wp_get_time": [vp, P(d), P(u64)],
         "wp_synchronize": [vp],
         "wp_profile_propagate": [vp, u64, P(d), P(u64)],
+        "wp_batch_create": [P(vp), C.c_uint32, vp, P(vp)],
+        "wp_batch_set_graph_steps": [vp, C.c_uint32],
+        "wp_batch_propagate": [vp, u64],
+        "wp_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -98,6 +102,8 @@ def _load() -> C.CDLL:
     L.wp_last_error.argtypes = [vp]
     L.wp_last_error.restype = C.c_char_p
     L.wp_version.restype = C.c_char_p
+    L.wp_batch_last_error.argtypes = [vp]
+    L.wp_batch_last_error.restype = C.c_char_p
     return L
 
 
@@ -268,3 +274,43 @@ def from_problem(prob, precision: Optional[str] = None, stream=None, order: str 
     s = Simulation(prob.grid, prob.pot, precision or prob.precision, stream=stream, order=order)
     s.set_gaussian(prob.init.center, prob.init.sigma, prob.init.k, prob.t0)
     return s
+
+
+class Batch:
+    """Several Simulations advanced together with shared launches (see
+    wp_batch_create).  The members stay usable for get_state/observables;
+    advance them through the batch while it exists."""
+
+    def __init__(self, sims, stream=None, graph_steps: int = 0):
+        import torch
+
+        if not sims:
+            raise ValueError("empty batch")
+        self.sims = list(sims)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        h = C.c_void_p()
+        rc = lib.wp_batch_create(arr, len(self.sims), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise WavepacketError(rc, "wp_batch_create")
+        self._h = h
+        if graph_steps:
+            self._check(lib.wp_batch_set_graph_steps(self._h, int(graph_steps)), "wp_batch_set_graph_steps")
+
+    def _check(self, rc: int, what: str) -> None:
+        if rc:
+            raise WavepacketError(rc, what, lib.wp_batch_last_error(self._h).decode())
+
+    def propagate(self, nsteps: int) -> None:
+        self._check(lib.wp_batch_propagate(self._h, int(nsteps)), "wp_batch_propagate")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.wp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
