@@ -16,6 +16,8 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import sys
@@ -74,6 +76,60 @@ def time_gpu(sim_mod, prob, precision, steps, warmup):
     return s, start.elapsed_time(end), wall
 
 
+def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int, ref_steps: int):
+    """The batched workload: `count` independent 2D driven traps of sizes
+    {128, 256, 512}^2 (seeded), FP32 state, advanced together; against the
+    same solves advanced one by one with FP64 launches (timed on a sample)."""
+    import torch
+
+    probs = W.batch_2d(count=count, seed=1306, steps=steps, precision="c64")
+    sites = sum(p.grid.points() for p in probs)
+    stream = torch.cuda.current_stream()
+    sims = [S.from_problem(p, stream=stream) for p in probs]
+    b = S.Batch(sims, stream=stream, graph_steps=graph_steps)
+    b.propagate(graph_steps + 1)  # warm-up: graph capture, first replay
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    b.propagate(steps)
+    end.record(stream)
+    end.synchronize()
+    ms = start.elapsed_time(end)
+    b.close()
+    # per-solve FP64 launches, one solve after another, on a sample
+    sample = probs[:ref_solves]
+    ref_sites = sum(p.grid.points() for p in sample)
+    refs = [S.from_problem(p, precision="c128", stream=stream) for p in sample]
+    refs[0].propagate(2)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for r in refs:
+        r.propagate(ref_steps)
+    end.record(stream)
+    end.synchronize()
+    ms_ref = start.elapsed_time(end)
+    # accuracy of the batched FP32 results: same solves, same steps, FP64 alone
+    errs = []
+    for p, s in list(zip(probs, sims))[:4]:
+        r = S.from_problem(p, precision="c128", stream=stream)
+        r.propagate(graph_steps + 1 + steps)
+        a, bb = s.get_state("c128"), r.get_state("c128")
+        errs.append(float(np.linalg.norm(a - bb) / np.linalg.norm(bb)))
+        r.close()
+    for x in sims + refs:
+        x.close()
+    sizes = {}
+    for p in probs:
+        sizes[p.grid.n[0]] = sizes.get(p.grid.n[0], 0) + 1
+    return {"workload": f"batch_2d_{count}", "solves": count, "sizes": sizes, "sites": sites, "steps": steps,
+            "graph_steps": graph_steps, "ms": round(ms, 3), "value": sites * steps / (ms / 1e3),
+            "unit": "site-steps/s", "dtype": "f32",
+            "per_solve_fp64": {"value": ref_sites * ref_steps / (ms_ref / 1e3), "unit": "site-steps/s",
+                               "sample": f"{ref_solves} solves x {ref_steps} steps, one after another"},
+            "speedup_vs_per_solve_fp64": (sites * steps / (ms / 1e3)) / (ref_sites * ref_steps / (ms_ref / 1e3)),
+            "max_rel_l2_vs_fp64": max(errs)}
+
+
 def cpu_baseline(prob, budget_s: float):
     import oracle
 
@@ -102,6 +158,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--also-c64x", action="store_true", help="also time the FP32-state / FP64-arithmetic mode")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-solves", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-graph-steps", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -183,6 +243,8 @@ def main() -> int:
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
     s32.close()
     torch.cuda.synchronize()
+    if not args.no_batch:
+        out["batch"] = batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.softcore_3d(n=args.n, precision="c128"), args.cpu_seconds)
     print(json.dumps(out), flush=True)

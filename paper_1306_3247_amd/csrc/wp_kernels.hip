@@ -53,7 +53,7 @@ __device__ __forceinline__ double step_time(const TimeDev &T, int64_t s, double 
 }
 
 template <class S, class R, int N>
-__device__ __forceinline__ void solve1d_body(const Solve1DArgs &a) {
+__device__ __forceinline__ void solve1d_body(const Solve1DArgs &a, int64_t nsteps) {
   using T = typename storage<S>::type;
   constexpr int L = fft_shape<N>::L, VPT = fft_shape<N>::VPT;
   static_assert(VPT <= 8, "one thread holds at most 8 values here");
@@ -96,7 +96,7 @@ __device__ __forceinline__ void solve1d_body(const Solve1DArgs &a) {
     }
   };
 
-  const int64_t ns = a.nsteps;
+  const int64_t ns = nsteps;
   if (!kvk) {
     for (int64_t s = 0; s < ns; ++s) {
       if (s == 0) apply_v(step_time(a.time, 0, 0.0), a.vtau_half);
@@ -128,15 +128,13 @@ __device__ __forceinline__ void solve1d_body(const Solve1DArgs &a) {
 
 template <class S, class R, int N>
 __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_kernel(Solve1DArgs a) {
-  solve1d_body<S, R, N>(a);
+  solve1d_body<S, R, N>(a, a.nsteps);
 }
 
 // One workgroup per solve.
 template <class S, class R, int N>
 __global__ void __launch_bounds__(fft_shape<N>::L) solve1d_batch_kernel(const Solve1DArgs *args, int64_t nsteps) {
-  Solve1DArgs a = args[blockIdx.x];
-  a.nsteps = nsteps;
-  solve1d_body<S, R, N>(a);
+  solve1d_body<S, R, N>(args[blockIdx.x], nsteps);
 }
 
 template <class S, class R, int N>

@@ -231,7 +231,9 @@ __global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
                                   (pass_cfg<S, R, N, STRIDED, KIND>::WAVES_EU))
     batch_pass_kernel(const PassArgs *args, const BatchItem *items, int nvar, int var, int row) {
   const BatchItem it = items[blockIdx.x];
-  const PassArgs a = args[it.solve * nvar + var];
+  // A reference into global memory, not a copy: the fields are read with
+  // scalar loads (the address is uniform), no private copy of the block.
+  const PassArgs &a = args[it.solve * nvar + var];
   pass_body<S, R, N, STRIDED, KIND>(a, a.coef ? a.coef + row * CO_COUNT : nullptr, (unsigned)it.tile);
 }
 
