@@ -145,7 +145,9 @@ wp_status wp_workspace_bytes(const wp_grid_desc *grid, uint64_t *bytes);
  * bound with wp_bind_state.  Errors: WP_EINVAL (bad descriptor: ndim not in 1..3, n not a power of
  * two or < 2 on a used axis, n != 1 on an unused axis, hi <= lo, mass <= 0,
  * hbar <= 0, dt = 0 or not finite, unknown kinds), WP_EUNSUPPORTED (an axis
- * longer than this build's line FFT: 8192 points for 1D, 4096 for 2D/3D),
+ * longer than this build supports: 2^20 points for 1D, where grids above
+ * 8192 points are transformed as [n1][n2] with twiddles in between, and
+ * 4096 per axis for 2D/3D),
  * WP_ENOMEM, WP_EDEVICE.  On success *out owns all device buffers. */
 wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void *stream,
                     wp_sim **out);
@@ -173,7 +175,8 @@ wp_status wp_set_state(wp_sim *sim, const double *host_psi_c128, double t0);
 /* Set psi(t0) to the Gaussian of Section 4.2,
  *   prod_d (2/pi)^(1/4) sigma_d^(-1/2) exp(-(x_d-c_d)^2/sigma_d^2 + i k_d (x_d-c_d)),
  * renormalised to unit discrete norm (k_d = p_d0/hbar).  Arrays hold one
- * entry per axis (3 entries; unused axes ignored).  sigma_d must be > 0. */
+ * entry per axis (3 entries; unused axes ignored).  sigma_d must be > 0.
+ * Asynchronous on the handle's stream (the arrays may be reused on return). */
 wp_status wp_set_state_gaussian(wp_sim *sim, const double center[3], const double sigma[3],
                                 const double k[3], double t0);
 
@@ -233,8 +236,10 @@ typedef struct wp_batch wp_batch;
  * they must outlive it, and while it exists they should be advanced only
  * through it.  Work is ordered on `stream` (hipStream_t or NULL).  Each
  * member's result equals its own wp_propagate result (same kernels, same
- * reduction order).  Errors: WP_EINVAL (count 0, NULL, a member in K-V-K
- * order), WP_ENOMEM, WP_EDEVICE. */
+ * reduction order).  The batch's work is ordered on `stream` only: work
+ * queued on members' own streams must be complete or on the same stream.
+ * Errors: WP_EINVAL (count 0, NULL, a member in K-V-K order), WP_ENOMEM,
+ * WP_EDEVICE. */
 wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_batch **out);
 
 /* Capture runs of k steady steps (1 <= k <= 64) of the 2D/3D members in a

@@ -22,6 +22,11 @@ struct wp_sim {
   hipStream_t stream = nullptr;
   int device = 0;
   int lg[3] = {0, 0, 0};
+  // Axes the line passes see: lg, except on a split 1D grid (more than
+  // kMaxLine1D points), which is transformed as [n1][n2] = [2^vlg[0]][2^vlg[1]].
+  bool split = false;
+  int vdim = 1;
+  int vlg[3] = {0, 0, 0};
   int64_t total = 0;
   int prec = 2;
   void *psi = nullptr;
@@ -33,6 +38,8 @@ struct wp_sim {
   cx<double> *d_tw[3] = {nullptr, nullptr, nullptr};
   double *d_partials = nullptr, *d_out8 = nullptr;
   double *d_coef = nullptr;  // waveform values for up to kCoefChunk steps
+  cx<double> *d_gauss = nullptr;  // per-axis factors of the last Gaussian state
+  cx<double> *d_wsplit = nullptr;  // split 1D: exp(-2 pi i e/n) as [n2] high and [n1] low factors
   int obs_blocks = 1;
   double t0 = 0.0;
   uint64_t step = 0;
@@ -105,7 +112,7 @@ std::string check_pot(const wp_potential_desc *p) {
 
 std::string check_supported(const wp_grid_desc *g) {
   if (g->ndim == 1) {
-    if (g->n[0] > (uint64_t)wp::kMaxLine1D) return "1D grids are limited to 8192 points in this build";
+    if (g->n[0] > (uint64_t)wp::kMaxSplit1D) return "1D grids are limited to 2^20 points in this build";
   } else {
     for (int d = 0; d < g->ndim; ++d)
       if (g->n[d] > (uint64_t)wp::kMaxLinePass) return "2D/3D axes are limited to 4096 points in this build";
@@ -150,11 +157,14 @@ wp::WaveDev to_dev(const wp_waveform &w) {
   return d;
 }
 
+// Allocate and fill a device array, ordered on `stream`.  Pageable sources
+// are consumed before hipMemcpyAsync returns, so `src` may go out of scope
+// afterwards; no device-wide synchronisation is involved.
 template <class T>
-hipError_t upload(T **dst, const std::vector<T> &src) {
+hipError_t upload(T **dst, const std::vector<T> &src, hipStream_t stream) {
   hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
   if (e != hipSuccess) return e;
-  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+  return hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, stream);
 }
 
 uint64_t table_bytes(const wp_grid_desc &g) {
@@ -173,6 +183,8 @@ void release(wp_sim *s) {
   if (s->d_partials) (void)hipFree(s->d_partials);
   if (s->d_out8) (void)hipFree(s->d_out8);
   if (s->d_coef) (void)hipFree(s->d_coef);
+  if (s->d_gauss) (void)hipFree(s->d_gauss);
+  if (s->d_wsplit) (void)hipFree(s->d_wsplit);
 }
 
 // Precision of the stored state (WP_C64X keeps an FP32 state).
@@ -201,10 +213,16 @@ wp::PassArgs pass_args(const wp_sim *s, int axis, uint32_t ops) {
   a.g = s->gd;
   a.axis = axis;
   int lgi = 0;
-  for (int d = axis + 1; d < 3; ++d) lgi += s->lg[d];
+  for (int d = axis + 1; d < 3; ++d) lgi += s->vlg[d];
   a.lg_inner = lgi;
-  a.n_lines = s->total >> s->lg[axis];
-  a.ops = ops;
+  a.n_lines = s->total >> s->vlg[axis];
+  // A split grid's potential and kinetic passes are its own kinds; a plain
+  // forward transform along axis 1 (for the energy) is an ordinary line FFT.
+  const bool split_kind = s->split && (axis == 0 || (ops & wp::OP_K));
+  a.ops = ops | (split_kind ? wp::OP_SPLIT : 0u);
+  a.wsplit[0] = s->d_wsplit;
+  a.wsplit[1] = s->split ? s->d_wsplit + ((size_t)1 << s->vlg[1]) : nullptr;
+  a.split_h = s->split ? s->vlg[0] : 0;
   a.coef = nullptr;
   a.vtau = 0.0;
   a.pot = s->pd;
@@ -272,6 +290,14 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
     s->gd.dx[d] = d < grid->ndim ? spacing(*grid, d) : 0.0;
   }
   s->gd.ndim = grid->ndim;
+  s->vdim = grid->ndim;
+  for (int d = 0; d < 3; ++d) s->vlg[d] = s->lg[d];
+  if (grid->ndim == 1 && grid->n[0] > (uint64_t)wp::kMaxLine1D) {
+    s->split = true;
+    s->vdim = 2;
+    s->vlg[0] = (s->lg[0] + 1) / 2;
+    s->vlg[1] = s->lg[0] / 2;
+  }
   for (int d = 0; d < 3; ++d) {
     s->pd.w[wp::CO_A + d] = to_dev(pot->a[d]);
     s->pd.w[wp::CO_B + d] = to_dev(pot->b[d]);
@@ -298,11 +324,26 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
       k2.push_back(ksq);
     }
   }
-  e = upload(&s->d_kfull, kf);
-  if (e == hipSuccess) e = upload(&s->d_khalf, kh);
-  if (e == hipSuccess) e = upload(&s->d_k2, k2);
+  e = upload(&s->d_kfull, kf, s->stream);
+  if (e == hipSuccess) e = upload(&s->d_khalf, kh, s->stream);
+  if (e == hipSuccess) e = upload(&s->d_k2, k2, s->stream);
   // Line-FFT twiddles per axis, in the stage order the kernels read them.
-  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = upload(&s->d_tw[d], stage_twiddles(grid->n[d]));
+  for (int d = 0; d < 3 && e == hipSuccess; ++d)
+    e = upload(&s->d_tw[d], stage_twiddles(uint64_t(1) << s->vlg[d]), s->stream);
+  if (e == hipSuccess && s->split) {
+    // exp(-2 pi i e/n), e = q*n1 + r: [n2] factors of q*n1 then [n1] of r.
+    const uint64_t n = grid->n[0], n1 = uint64_t(1) << s->vlg[0], n2 = uint64_t(1) << s->vlg[1];
+    std::vector<cx<double>> w;
+    for (uint64_t q = 0; q < n2; ++q) {
+      const double a = -2.0 * kPi * (double)(q * n1) / (double)n;
+      w.push_back({std::cos(a), std::sin(a)});
+    }
+    for (uint64_t r = 0; r < n1; ++r) {
+      const double a = -2.0 * kPi * (double)r / (double)n;
+      w.push_back({std::cos(a), std::sin(a)});
+    }
+    e = upload(&s->d_wsplit, w, s->stream);
+  }
   if (e == hipSuccess) {
     int64_t b = (s->total + wp::kObsThreads - 1) / wp::kObsThreads;
     s->obs_blocks = (int)(b > 1024 ? 1024 : b);
@@ -406,12 +447,14 @@ wp_status wp_set_state_gaussian(wp_sim *s, const double center[3], const double 
   }
   hipError_t e = ensure_state(s);
   if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
-  cx<double> *d[3] = {nullptr, nullptr, nullptr};
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = upload(&d[i], f[i]);
+  if (!s->d_gauss) {
+    e = hipMalloc((void **)&s->d_gauss, sizeof(cx<double>) * (s->g.n[0] + s->g.n[1] + s->g.n[2]));
+    if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
+  }
+  cx<double> *d[3] = {s->d_gauss, s->d_gauss + s->g.n[0], s->d_gauss + s->g.n[0] + s->g.n[1]};
+  for (int i = 0; i < 3 && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(d[i], f[i].data(), sizeof(cx<double>) * f[i].size(), hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = wp::launch_gaussian(storage_prec(s), s->psi, s->gd, d[0], d[1], d[2], s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  for (auto p : d)
-    if (p) (void)hipFree(p);
   if (e != hipSuccess) return hip_fail(s, e, "set_state_gaussian");
   s->t0 = t0;
   s->step = 0;
@@ -464,7 +507,7 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
     *out = s->d_coef + (n - cbase) * wp::CO_COUNT;
     return hipSuccess;
   };
-  if (s->g.ndim == 1) {
+  if (s->g.ndim == 1 && !s->split) {
     wp::Solve1DArgs a{};
     a.psi = s->psi;
     a.g = s->gd;
@@ -483,7 +526,7 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
     a.tw = s->d_tw[0];
     return launch(WP_PASS_SOLVE1D, [&]() { return wp::launch_solve1d(prec, a, st); });
   }
-  const int last = s->g.ndim - 1;
+  const int last = s->vdim - 1;
   // Middle of a step (all axes but the first): forward over axes 1..last-1,
   // forward + kinetic + inverse along the last axis, inverse back.
   auto middle = [&](bool half_k) -> hipError_t {
@@ -646,14 +689,12 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
   if (e == hipSuccess && energy) {
     if (!s->scratch) e = hipMalloc(&s->scratch, s->psi_bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
-    for (int d = 0; d < s->g.ndim && e == hipSuccess; ++d) {
+    for (int d = 0; d < s->vdim && e == hipSuccess; ++d) {
       wp::PassArgs p = pass_args(s, d, wp::OP_FWD);
       p.psi = s->scratch;
-      if (s->g.ndim == 1) {
-        if (!wp::pass_supported(s->prec, s->lg[0])) {
-          e = hipErrorNotSupported;
-          break;
-        }
+      if (!wp::pass_supported(s->prec, s->vlg[d])) {
+        e = hipErrorNotSupported;
+        break;
       }
       e = wp::launch_pass(s->prec, p, s->stream);
     }
@@ -662,6 +703,7 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
       k.psi = s->scratch;
       k.kinetic = 1;
       k.with_v = 0;
+      k.split_h = s->split ? s->vlg[0] : 0;
       int off = 0;
       for (int d = 0; d < 3; ++d) {
         k.k2tab[d] = s->d_k2 + off;
@@ -739,6 +781,8 @@ struct wp_batch {
   wp::Solve1DArgs *d_args1d = nullptr;
   wp::PotDev *d_pots = nullptr;
   double *d_t0 = nullptr, *d_dt = nullptr, *d_coef = nullptr;
+  // Step counters: [0, count) for the pass schedule (advanced on the device),
+  // [count, 2 count) read by the 1D solvers.
   int64_t *d_step = nullptr;
   std::vector<PassGroup> groups;
   std::vector<Group1D> groups1d;
@@ -750,6 +794,11 @@ struct wp_batch {
   // ordered after and before the caller's work by events.
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // With both 1D and multi-axis members, the 1D solvers (a few workgroups
+  // each, running all steps) go to a stream of their own so that they run
+  // beside the pass launches instead of before them.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
 };
 
@@ -761,6 +810,9 @@ void batch_release(wp_batch *b) {
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->side) (void)hipStreamDestroy(b->side);
   for (void *p : {(void *)b->d_args, (void *)b->d_items, (void *)b->d_args1d, (void *)b->d_pots, (void *)b->d_t0,
                   (void *)b->d_dt, (void *)b->d_coef, (void *)b->d_step})
     if (p) (void)hipFree(p);
@@ -830,7 +882,6 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
   b->stream = (hipStream_t)stream;
   hipError_t e = hipGetDevice(&b->device);
   for (uint32_t i = 0; i < count && e == hipSuccess; ++i) e = ensure_state(b->sims[i]);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
   // Per-solve host descriptors.
   std::vector<wp::PassArgs> args((size_t)count * kVariants);
   std::vector<wp::PotDev> pots(count);
@@ -857,13 +908,13 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     t0[i] = s->t0;
     dt[i] = s->g.dt;
     steps[i] = (int64_t)s->step;
-    if (s->g.ndim == 1) {
+    if (s->g.ndim == 1 && !s->split) {
       members1d[{s->prec, s->lg[0]}].push_back((int)i);
       continue;
     }
     const double tau_half = 0.5 * s->g.dt / s->g.hbar, tau_full = s->g.dt / s->g.hbar;
     const double *coef = b->d_coef + (size_t)i * b->rows * wp::CO_COUNT;
-    const int last = s->g.ndim - 1;
+    const int last = s->vdim - 1;
     wp::PassArgs *A = &args[(size_t)i * kVariants];
     A[V_FIRST] = pass_args(s, 0, wp::OP_V | wp::OP_FWD);
     A[V_FIRST].vtau = tau_half;
@@ -873,20 +924,20 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     A[V_LAST].vtau = tau_half;
     for (int v : {V_FIRST, V_STEADY, V_LAST}) A[v].coef = coef;
     A[K_LAST] = pass_args(s, last, wp::OP_FWD | wp::OP_K | wp::OP_POST_INV);
-    if (s->g.ndim == 3) {
+    if (s->vdim == 3) {
       A[F_FWD] = pass_args(s, 1, wp::OP_FWD);
       A[F_INV] = pass_args(s, 1, wp::OP_PRE_INV);
     }
     auto add = [&](int slot, int axis, int kind) {
       const wp::PassArgs &pa = A[slot == SLOT_V ? V_FIRST : slot == SLOT_K ? K_LAST : slot == SLOT_FFWD ? F_FWD : F_INV];
       const bool strided = pa.lg_inner > 0;
-      const int tile = wp::pass_tile(s->prec, s->lg[axis], strided, kind);
+      const int tile = wp::pass_tile(s->prec, s->vlg[axis], strided, kind);
       const int64_t tiles = (pa.n_lines + tile - 1) / tile;
-      members[{slot, s->prec, s->lg[axis], kind, strided}].push_back({(int)i, tiles});
+      members[{slot, s->prec, s->vlg[axis], kind, strided}].push_back({(int)i, tiles});
     };
-    add(SLOT_V, 0, 1);
-    add(SLOT_K, last, 2);
-    if (s->g.ndim == 3) {
+    add(SLOT_V, 0, s->split ? 3 : 1);
+    add(SLOT_K, last, s->split ? 4 : 2);
+    if (s->vdim == 3) {
       add(SLOT_FFWD, 1, 0);
       add(SLOT_FINV, 1, 0);
     }
@@ -924,17 +975,22 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
       b->groups1d.push_back(g);
     }
   }
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_step, sizeof(int64_t) * count);
-  // The 1D argument blocks read their step from the device counters.
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_step, sizeof(int64_t) * 2 * count);
+  // The 1D argument blocks read their step from the second set of counters.
   for (size_t j = 0, gi = 0; e == hipSuccess && gi < b->groups1d.size(); ++gi)
-    for (int i : members1d[{b->groups1d[gi].prec, b->groups1d[gi].lgN}]) a1d[j++].time.step_dev = b->d_step + i;
-  if (e == hipSuccess) e = upload(&b->d_args, args);
-  if (e == hipSuccess && !items.empty()) e = upload(&b->d_items, items);
-  if (e == hipSuccess && !a1d.empty()) e = upload(&b->d_args1d, a1d);
-  if (e == hipSuccess) e = upload(&b->d_pots, pots);
-  if (e == hipSuccess) e = upload(&b->d_t0, t0);
-  if (e == hipSuccess) e = upload(&b->d_dt, dt);
-  if (e == hipSuccess) e = hipMemcpy(b->d_step, steps.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice);
+    for (int i : members1d[{b->groups1d[gi].prec, b->groups1d[gi].lgN}])
+      a1d[j++].time.step_dev = b->d_step + count + i;
+  if (e == hipSuccess && !b->groups1d.empty() && !b->groups.empty()) {
+    e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = upload(&b->d_args, args, b->stream);
+  if (e == hipSuccess && !items.empty()) e = upload(&b->d_items, items, b->stream);
+  if (e == hipSuccess && !a1d.empty()) e = upload(&b->d_args1d, a1d, b->stream);
+  if (e == hipSuccess) e = upload(&b->d_pots, pots, b->stream);
+  if (e == hipSuccess) e = upload(&b->d_t0, t0, b->stream);
+  if (e == hipSuccess) e = upload(&b->d_dt, dt, b->stream);
   if (e != hipSuccess) {
     batch_release(b);
     delete b;
@@ -957,14 +1013,19 @@ wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps) {
   (void)hipSetDevice(b->device);
   const int count = (int)b->sims.size();
   // The members' host counters are authoritative: refresh the device copy.
-  std::vector<int64_t> steps(count);
-  for (int i = 0; i < count; ++i) steps[i] = (int64_t)b->sims[i]->step;
-  hipError_t e = hipMemcpyAsync(b->d_step, steps.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  std::vector<int64_t> steps(2 * (size_t)count);
+  for (int i = 0; i < count; ++i) steps[i] = steps[count + i] = (int64_t)b->sims[i]->step;
+  hipError_t e = hipMemcpyAsync(b->d_step, steps.data(), sizeof(int64_t) * 2 * count, hipMemcpyHostToDevice,
+                                b->stream);
   // 1D members: all steps in one launch per line-length class.
+  hipStream_t st1d = b->side ? b->side : b->stream;
+  if (e == hipSuccess && b->side) {
+    e = hipEventRecord(b->ev_fork, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+  }
   for (const Group1D &g : b->groups1d) {
     if (e != hipSuccess) break;
-    e = wp::launch_solve1d_batch(g.prec, g.lgN, b->d_args1d + g.off, (int)g.count, (int64_t)nsteps, b->stream);
+    e = wp::launch_solve1d_batch(g.prec, g.lgN, b->d_args1d + g.off, (int)g.count, (int64_t)nsteps, st1d);
   }
   // 2D/3D members: open (potential half step at t_n and forward transform of
   // the first axis), nsteps-1 steady steps, and a final step closing with the
@@ -1015,6 +1076,10 @@ wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps) {
     if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_K, K_LAST, 0);
     if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_FINV, F_INV, 0);
     if (e == hipSuccess) e = run_slot(b, b->stream, SLOT_V, V_LAST, 1);
+  }
+  if (e == hipSuccess && b->side) {
+    e = hipEventRecord(b->ev_join, b->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join, 0);
   }
   if (e != hipSuccess) return bfail(b, WP_EDEVICE, std::string("batch_propagate: ") + hipGetErrorString(e));
   for (wp_sim *s : b->sims) s->step += nsteps;

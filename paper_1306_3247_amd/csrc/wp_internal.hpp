@@ -15,6 +15,11 @@ enum : uint32_t {
   OP_FWD = 1u << 2,       // forward line FFT
   OP_K = 1u << 3,         // multiply by the kinetic factor (1/N folded in)
   OP_POST_INV = 1u << 4,  // inverse line FFT
+  // A 1D grid of n = n1*n2 points transformed as [n1][n2] (a four-step
+  // transform): the pass along axis 0 applies the twiddles exp(-+2 pi i j2 k1/n)
+  // next to its transforms, the pass along axis 1 the kinetic factor of bin
+  // k1 + n1*k2.
+  OP_SPLIT = 1u << 5,
 };
 
 struct GridDev {
@@ -49,6 +54,10 @@ struct PassArgs {
   PotDev pot;
   const cx<double> *ktab[3];  // kinetic factors per axis (OP_K)
   const cx<double> *tw;       // twiddles exp(-2 pi i e/N), e < N
+  // OP_SPLIT: exp(-2 pi i e/n) = wsplit[0][e >> split_h] * wsplit[1][e & (2^split_h - 1)]
+  // for 0 <= e < n = 2^g.lg[0]; split_h = log2 n1.
+  const cx<double> *wsplit[2];
+  int32_t split_h;
 };
 
 struct Solve1DArgs {
@@ -75,6 +84,9 @@ struct ObsArgs {
   PotDev pot;
   const double *k2tab[3];  // k^2 per axis (kinetic)
   double *partials;        // [blocks][8]
+  // kinetic on a split 1D grid: point i = k1*n2 + k2 holds bin k1 + n1*k2,
+  // n1 = 2^split_h (0: not split)
+  int32_t split_h;
 };
 
 // One workgroup of a batched pass: tile `tile` of solve `solve`.
@@ -92,7 +104,7 @@ struct BatchLaunch {
   int nvar, var, row;
   int lgN;
   bool strided;
-  int kind;  // 0 FFT only, 1 potential, 2 kinetic
+  int kind;  // 0 FFT only, 1 potential, 2 kinetic, 3 / 4 split 1D potential / kinetic
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -111,6 +123,8 @@ hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, dou
 // single-workgroup 1D solver.
 constexpr int kMaxLinePass = 4096;
 constexpr int kMaxLine1D = 8192;
+// Longer 1D grids use the split transform: n1, n2 between 128 and 1024.
+constexpr int kMaxSplit1D = 1 << 20;
 constexpr int kObsThreads = 256;
 constexpr int kCoefChunk = 1024;  // steps per coefficient table
 

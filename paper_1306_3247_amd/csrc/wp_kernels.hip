@@ -35,7 +35,9 @@ int pass_tile(int prec, int lgN, bool strided, int kind) {
 bool pass_supported(int prec, int lgN) { return prec >= 1 && prec <= 3 && lgN >= 1 && lgN <= 12; }
 
 hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s) {
-  const int lgN = a.g.lg[a.axis];
+  // Line length: the axis length, or on a split 1D grid n1 = 2^split_h
+  // (axis 0) and n2 = n/n1 (axis 1).
+  const int lgN = a.split_h > 0 ? (a.axis == 0 ? a.split_h : a.g.lg[0] - a.split_h) : a.g.lg[a.axis];
   if (!pass_supported(prec, lgN)) return hipErrorInvalidValue;
   if ((a.ops & OP_V) && (a.ops & OP_K)) return hipErrorInvalidValue;
   if (prec == 2) return dispatch_pass_c128(lgN, a, s);
@@ -315,7 +317,12 @@ __global__ void __launch_bounds__(kObsThreads) obs_kernel(ObsArgs a) {
     const double w = pr * pr + pi * pi;
     const int i2 = (int)(i & m2), i1 = (int)((i >> a.g.lg[2]) & m1);
     const int i0 = (int)(i >> (a.g.lg[1] + a.g.lg[2]));
-    if (a.kinetic) {
+    if (a.kinetic && a.split_h) {
+      // split 1D: point k1*n2 + k2 holds bin k1 + n1*k2
+      const int lg2 = a.g.lg[0] - a.split_h;
+      const int64_t m = (i >> lg2) + ((i & (((int64_t)1 << lg2) - 1)) << a.split_h);
+      acc[0] += a.k2tab[0][m] * w;
+    } else if (a.kinetic) {
       acc[0] += (a.k2tab[0][i0] + a.k2tab[1][i1] + a.k2tab[2][i2]) * w;
     } else {
       const double x0 = a.g.lo[0] + (double)i0 * a.g.dx[0];

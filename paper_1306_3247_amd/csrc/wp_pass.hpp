@@ -5,7 +5,11 @@
 //   PK_F  forward or inverse FFT only (middle axes of a 3D step);
 //   PK_V  [inverse FFT] potential phase [forward FFT] (first axis): the
 //         potential is evaluated on the device at the current time;
-//   PK_K  forward FFT, kinetic phase, inverse FFT (last axis).
+//   PK_K  forward FFT, kinetic phase, inverse FFT (last axis);
+//   PK_VS, PK_KS  the two passes of a split 1D grid (OP_SPLIT): PK_VS is
+//         [twiddle* inverse FFT] potential phase [forward FFT twiddle] along
+//         axis 0 of [n1][n2], PK_KS forward FFT, kinetic phase, inverse FFT
+//         along axis 1.
 // Workgroup shapes are chosen per (precision, N, layout, kind) so that two or
 // more workgroups fit in a CU's 160 KiB of LDS, letting one workgroup load
 // while another computes.
@@ -16,7 +20,7 @@
 
 namespace wp {
 
-enum PassKind : int { PK_F = 0, PK_V = 1, PK_K = 2 };
+enum PassKind : int { PK_F = 0, PK_V = 1, PK_K = 2, PK_VS = 3, PK_KS = 4 };
 
 constexpr int pow2_floor(int x) {
   int p = 1;
@@ -31,8 +35,9 @@ struct pass_cfg {
   static constexpr int ELEM = (int)sizeof(cx<R>);   // LDS element (compute type)
   static constexpr int GELEM = (int)sizeof(cx<S>);  // HBM element (storage type)
   // 16 values per thread in FP32 (8 in FP64) halves the threads per line;
-  // potential passes keep 8, whose FP64 phase evaluation needs the registers.
-  static constexpr int VPT = (ELEM == 8 && N >= 16) ? 16 : (N < 8 ? N : 8);
+  // the split 1D potential pass, with a twiddle and an FP64 phase per value,
+  // keeps 8 to stay within its registers.
+  static constexpr int VPT = (ELEM == 8 && N >= 16 && KIND != PK_VS) ? 16 : (N < 8 ? N : 8);
   static constexpr int L = N / VPT;
   static constexpr bool EXCH = N > 8;  // more than one stage: exchanges through LDS
   // Padded line length (see pad16).
@@ -93,6 +98,13 @@ __device__ __forceinline__ double coord(const GridDev &g, int d, int i) {
   return g.lo[d] + (double)i * g.dx[d];
 }
 
+// exp(-2 pi i e/n) of a split 1D grid, from two short tables (e taken mod n).
+__device__ __forceinline__ cx<double> split_twiddle(const PassArgs &a, int64_t e) {
+  e &= ((int64_t)1 << a.g.lg[0]) - 1;
+  const int h = a.split_h;
+  return cmul(a.wsplit[0][e >> h], a.wsplit[1][e & ((1 << h) - 1)]);
+}
+
 // The work of one workgroup: tile `blk` of the lines described by `a`;
 // `coef` holds the CO_COUNT waveform values at the pass's time (kind V).
 template <class S, class R, int N, bool STRIDED, int KIND>
@@ -146,6 +158,57 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
   if constexpr (KIND == PK_F) {
     if (ops & OP_PRE_INV) line_fft<N, VPT, true>(v, t, tw, lds);
     else line_fft<N, VPT, false>(v, t, tw, lds);
+  } else if constexpr (KIND == PK_KS) {
+    // Line k1 of [n1][n2]; after the forward transform position k2 holds
+    // bin k1 + n1*k2 of the n-point transform (index taken mod n, so that
+    // the idle lanes of a partial tile stay inside the table).
+    const int64_t nmask = ((int64_t)1 << a.g.lg[0]) - 1;
+    const cx<double> *kt = a.ktab[0];
+    line_fft<N, VPT, false>(v, t, tw, lds);
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], kt[(line + a.n_lines * (int64_t)(t + L * u)) & nmask]);
+    line_fft<N, VPT, true>(v, t, tw, lds);
+  } else if constexpr (KIND == PK_VS) {
+    // Column j2 = line of [n1][n2]; position j1 along it is the grid point
+    // j1*n2 + j2.  Between the two line transforms of the n-point transform
+    // sit the twiddles exp(-2 pi i j2 k1/n) (forward) and their conjugates
+    // (inverse).
+    const int64_t j2 = line;
+    const int lg2 = lgi;
+    if (ops & OP_PRE_INV) {
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const cx<double> w = split_twiddle(a, j2 * (int64_t)(t + L * u));
+        v[u] = mul_acc(v[u], cx<double>{w.x, -w.y});
+      }
+      line_fft<N, VPT, true>(v, t, tw, lds);
+    }
+    if (ops & OP_V) {
+      const double *s_coef = coef;  // uniform: scalar loads
+      const double vt = a.vtau;
+      const double cc = vt * s_coef[CO_C], ca = vt * s_coef[CO_A], cb = vt * s_coef[CO_B];
+      const double cs = vt * s_coef[CO_S];
+      const int kind = a.pot.v0_kind;
+      const double p0 = a.pot.v0_par[0], p1 = a.pot.v0_par[1], p2 = a.pot.v0_par[2];
+      const double lo = a.g.lo[0], dx = a.g.dx[0];
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const double x = lo + (double)(((int64_t)(t + L * u) << lg2) + j2) * dx;
+        double th = cc + x * fma(cb, x, ca);
+        if (kind == 1) {
+          th -= cs * p0 * rsqrt(fma(x, x, p1));
+        } else if (kind == 2) {
+          const double e = 1.0 - exp(-p1 * (x - p2));
+          th += cs * p0 * e * e;
+        }
+        v[u] = mul_acc(v[u], expmi_wave(th));
+      }
+    }
+    if (ops & OP_FWD) {
+      line_fft<N, VPT, false>(v, t, tw, lds);
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], split_twiddle(a, j2 * (int64_t)(t + L * u)));
+    }
   } else if constexpr (KIND == PK_K) {
     // Kinetic factor of this line on the other axes (1/N is in the table of
     // the last axis).
@@ -247,6 +310,12 @@ hipError_t launch_batch_t(const BatchLaunch &b, hipStream_t s) {
 
 template <class S, class R, int N>
 hipError_t launch_batch_n(const BatchLaunch &b, hipStream_t s) {
+  if constexpr (N >= 128 && N <= 1024) {
+    if (b.kind == PK_VS) return launch_batch_t<S, R, N, true, PK_VS>(b, s);
+    if (b.kind == PK_KS) return launch_batch_t<S, R, N, false, PK_KS>(b, s);
+  } else {
+    if (b.kind == PK_VS || b.kind == PK_KS) return hipErrorInvalidValue;
+  }
   if (b.kind == PK_V) return b.strided ? launch_batch_t<S, R, N, true, PK_V>(b, s) : launch_batch_t<S, R, N, false, PK_V>(b, s);
   if (b.kind == PK_K) return b.strided ? launch_batch_t<S, R, N, true, PK_K>(b, s) : launch_batch_t<S, R, N, false, PK_K>(b, s);
   return b.strided ? launch_batch_t<S, R, N, true, PK_F>(b, s) : launch_batch_t<S, R, N, false, PK_F>(b, s);
@@ -276,6 +345,12 @@ template <class S, class R>
 int pass_tile_t(int lgN, bool strided, int kind) {
   auto pick = [&](auto n) -> int {
     constexpr int NN = decltype(n)::value;
+    if constexpr (NN >= 128 && NN <= 1024) {
+      if (kind == PK_VS) return pass_cfg<S, R, NN, true, PK_VS>::TILE;
+      if (kind == PK_KS) return pass_cfg<S, R, NN, false, PK_KS>::TILE;
+    } else {
+      if (kind == PK_VS || kind == PK_KS) return 0;
+    }
     if (kind == PK_V) return strided ? pass_cfg<S, R, NN, true, PK_V>::TILE : pass_cfg<S, R, NN, false, PK_V>::TILE;
     if (kind == PK_K) return strided ? pass_cfg<S, R, NN, true, PK_K>::TILE : pass_cfg<S, R, NN, false, PK_K>::TILE;
     return strided ? pass_cfg<S, R, NN, true, PK_F>::TILE : pass_cfg<S, R, NN, false, PK_F>::TILE;
@@ -308,6 +383,13 @@ hipError_t launch_pass_t(const PassArgs &a, hipStream_t s) {
 template <class S, class R, int N>
 hipError_t launch_pass_n(const PassArgs &a, hipStream_t s) {
   const bool strided = a.lg_inner > 0;
+  if (a.ops & OP_SPLIT) {
+    if constexpr (N >= 128 && N <= 1024) {
+      if (a.axis == 0 && strided) return launch_pass_t<S, R, N, true, PK_VS>(a, s);
+      if (a.axis == 1 && !strided) return launch_pass_t<S, R, N, false, PK_KS>(a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (a.ops & OP_V) return strided ? launch_pass_t<S, R, N, true, PK_V>(a, s) : launch_pass_t<S, R, N, false, PK_V>(a, s);
   if (a.ops & OP_K) return strided ? launch_pass_t<S, R, N, true, PK_K>(a, s) : launch_pass_t<S, R, N, false, PK_K>(a, s);
   return strided ? launch_pass_t<S, R, N, true, PK_F>(a, s) : launch_pass_t<S, R, N, false, PK_F>(a, s);

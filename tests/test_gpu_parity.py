@@ -66,6 +66,44 @@ def test_1d_random_state(S, W, oracle_mod, n, order, precision):
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
+@pytest.mark.parametrize("order", ["vkv", "kvk"])
+@pytest.mark.parametrize("n", [16384, 32768, 65536, 1 << 20])
+def test_1d_split_random_state(S, W, oracle_mod, n, order, precision):
+    """1D grids beyond the single-workgroup solver: the [n1][n2] split
+    transform (n1 = n2 and n1 = 2 n2), up to the largest supported length."""
+    prob = W.driven_ho_1d(n=n, steps=5, precision=precision)
+    psi0 = W.random_state((n,), seed=n + 1)
+    psi0 /= np.linalg.norm(psi0)
+    got, ref, _ = run_both(S, oracle_mod, prob, psi0, order)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_1d_split_driven_trap(S, W, oracle_mod, precision):
+    """The serving mix's largest 1D request shape: 2^16 points on [-20, 20),
+    driven trap, 300 steps from a Gaussian."""
+    prob = W.driven_trap(1, 65536, E0=0.15, omega=1.3, center=[1.5], k=[-0.5], steps=300,
+                         precision=precision, half_width=20.0)
+    got, ref, psi0 = run_both(S, oracle_mod, prob)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("v0", ["morse", "softcore"])
+def test_1d_split_nonseparable(S, W, oracle_mod, v0, precision):
+    """Per-point potentials on a split grid: the Morse oscillator and a 1D
+    soft-core well."""
+    prob = morse_dipole_1d(W, 16384, 40, precision)
+    if v0 == "softcore":
+        prob.grid.lo, prob.grid.hi = [-30.0], [30.0]
+        prob.pot.v0_kind, prob.pot.v0_par = "softcore", (1.0, 2.0, 0.0, 0.0)
+        prob.grid.mass = 1.0
+        prob.init = W.Gaussian([0.0], [1.0], [0.5])
+    got, ref, _ = run_both(S, oracle_mod, prob)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
 def test_1d_morse(S, W, oracle_mod, precision):
     prob = morse_dipole_1d(W, 512, 100, precision)
     got, ref, _ = run_both(S, oracle_mod, prob)
@@ -123,10 +161,14 @@ def test_softcore_3d_scaled(S, W, oracle_mod, precision):
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
-@pytest.mark.parametrize("which", ["1d", "2d", "3d"])
+@pytest.mark.parametrize("which", ["1d", "1d_split", "2d", "3d"])
 def test_observables(S, W, oracle_mod, which, precision):
     if which == "1d":
         prob = morse_dipole_1d(W, 1024, 30, precision)
+        prob.t0 = 1.0
+    elif which == "1d_split":
+        prob = W.driven_trap(1, 32768, E0=0.1, omega=1.0, center=[-2.0], k=[1.0], steps=30,
+                             precision=precision, half_width=20.0)
         prob.t0 = 1.0
     elif which == "2d":
         prob = W.modulated_trap_2d(n=128, steps=30, precision=precision, half_width=8.0)
