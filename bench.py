@@ -130,6 +130,60 @@ def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int,
             "max_rel_l2_vs_fp64": max(errs)}
 
 
+def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int, graph_steps: int,
+                budget_gib: float, ref_count: int):
+    """The serving workload: Poisson request streams (60% 1D 2^10..2^16, 30%
+    2D 128..1024^2, 10% 3D 64..256^3, 500..5000 steps, FP32 state) served with
+    admission by HBM budget and continuous batching.  Rates are fractions of
+    the closed-loop capacity (every request present at time zero)."""
+    import torch
+
+    kw = dict(budget_bytes=int(budget_gib * (1 << 30)), tick_steps=tick, graph_steps=graph_steps)
+    cap_reqs = W.serving_stream(cap_count, float("inf"), seed=1306)
+    cap_rep = V.Server(**kw).run(cap_reqs)
+    cap = cap_rep.summary()
+    C = cap["requests_per_s"]
+    runs = []
+    for i, f in enumerate(rates):
+        reqs = W.serving_stream(warm + count, f * C, seed=1306 + 1 + i)
+        keep = {r.rid for r in reqs[warm:warm + 3]} if i == 0 else False
+        rep = V.Server(keep_results=keep, **kw).run(reqs)
+        s = rep.summary(first_rid=warm)
+        s.update({"rate_frac": f, "rate_hz": f * C})
+        runs.append(s)
+        if i == 0:
+            kept = [(r, x) for r, x in zip(reqs, rep.served) if x.result is not None]
+    # per-solve FP64 launches, one solve after another, on the first requests
+    ref = W.serving_stream(ref_count, float("inf"), seed=1306)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ref_sites = 0
+    for r in ref:
+        s = S.from_problem(r.problem, precision="c128", stream=stream)
+        s.propagate(r.problem.steps)
+        s.synchronize()
+        s.close()
+        ref_sites += r.problem.grid.points() * r.problem.steps
+    ref_rate = ref_sites / (time.perf_counter() - t)
+    # accuracy of served FP32 results against the same solves in FP64
+    errs = []
+    for r, x in kept:
+        s = S.from_problem(r.problem, precision="c128", stream=stream)
+        s.propagate(r.problem.steps)
+        y = s.get_state("c128")
+        s.close()
+        errs.append(float(np.linalg.norm(x.result.astype(np.complex128) - y) / np.linalg.norm(y)))
+    best = max(runs, key=lambda z: z["site_steps_per_s"])
+    return {"workload": "serving_poisson_mixed", "capacity_req_per_s": C, "capacity": cap,
+            "runs": runs, "tick_steps": tick, "graph_steps": graph_steps, "budget_gib": budget_gib,
+            "per_solve_fp64": {"value": ref_rate, "unit": "site-steps/s",
+                               "sample": f"first {ref_count} requests of the closed-loop stream, one after another"},
+            "speedup_vs_per_solve_fp64": best["site_steps_per_s"] / ref_rate,
+            "max_rel_l2_vs_fp64": max(errs) if errs else None,
+            "accuracy_sample": [r.problem.name for r, _ in kept]}
+
+
 def cpu_baseline(prob, budget_s: float):
     import oracle
 
@@ -162,6 +216,14 @@ def main() -> int:
     ap.add_argument("--batch-solves", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-graph-steps", type=int, default=16)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300, help="measured requests per arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=30, help="requests served before the measured ones")
+    ap.add_argument("--serve-rates", type=str, default="0.5,0.9", help="fractions of the closed-loop capacity")
+    ap.add_argument("--serve-capacity-requests", type=int, default=200)
+    ap.add_argument("--serve-tick", type=int, default=250)
+    ap.add_argument("--serve-graph-steps", type=int, default=16)
+    ap.add_argument("--serve-budget-gib", type=float, default=192.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -245,6 +307,13 @@ def main() -> int:
     torch.cuda.synchronize()
     if not args.no_batch:
         out["batch"] = batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200)
+    if not args.no_serve:
+        from paper_1306_3247_amd import serve as V
+
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        out["serving"] = serve_bench(S, W, V, args.serve_requests, args.serve_warmup, rates,
+                                     args.serve_capacity_requests, args.serve_tick, args.serve_graph_steps,
+                                     args.serve_budget_gib, 20)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.softcore_3d(n=args.n, precision="c128"), args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -162,24 +162,30 @@ class Request:
 
 
 def serving_stream(count: int, rate_hz: float, seed: int = 1306,
-                   max_1d_log2: int = 13, max_3d: int = 256,
-                   steps_range=(500, 5000), precision: str = "c64") -> List[Request]:
-    """Poisson arrivals at `rate_hz`; mix 60% 1D (n = 2^k, k in [10, max_1d_log2]),
-    30% 2D (n in {128, 256, 512, 1024}), 10% 3D (n in {64, 128, max_3d}), each a
-    driven trap with E0 ~ U[0.01, 0.2], omega ~ U[0.5, 2], seeded Gaussian and
-    a step count uniform in steps_range."""
+                   log2_1d: Sequence[int] = (10, 16), sizes_2d: Sequence[int] = (128, 256, 512, 1024),
+                   sizes_3d: Sequence[int] = (64, 128, 256), steps_range=(500, 5000),
+                   precision: str = "c64", fractions=(0.6, 0.3)) -> List[Request]:
+    """Poisson arrivals at `rate_hz` (exponential gaps; rate_hz = inf puts
+    every arrival at 0).  Mix: fractions[0] 1D with n = 2^k, k uniform in
+    log2_1d (inclusive), on [-20, 20); fractions[1] 2D with n uniform in
+    sizes_2d, on [-16, 16)^2; the rest 3D with n uniform in sizes_3d, on
+    [-16, 16)^3.  Each is a driven trap V = |x|^2/2 - E0 x sin(omega t), E0 ~
+    U[0.01, 0.2], omega ~ U[0.5, 2], Gaussian centre ~ U[-3, 3]^d, k ~
+    U[-1, 1]^d, sigma 1, dt = 0.01, steps uniform in steps_range (inclusive),
+    drawn per request in this order from numpy's default_rng(seed)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     reqs = []
     for i in range(count):
-        t += float(rng.exponential(1.0 / rate_hz))
+        if np.isfinite(rate_hz):
+            t += float(rng.exponential(1.0 / rate_hz))
         u = float(rng.uniform())
-        if u < 0.6:
-            ndim, n = 1, 1 << int(rng.integers(10, max_1d_log2 + 1))
-        elif u < 0.9:
-            ndim, n = 2, int(rng.choice([128, 256, 512, 1024]))
+        if u < fractions[0]:
+            ndim, n = 1, 1 << int(rng.integers(log2_1d[0], log2_1d[1] + 1))
+        elif u < fractions[0] + fractions[1]:
+            ndim, n = 2, int(rng.choice(list(sizes_2d)))
         else:
-            ndim, n = 3, int(rng.choice([s for s in (64, 128, 256) if s <= max_3d]))
+            ndim, n = 3, int(rng.choice(list(sizes_3d)))
         E0 = float(rng.uniform(0.01, 0.2))
         omega = float(rng.uniform(0.5, 2.0))
         c = rng.uniform(-3.0, 3.0, size=ndim)
