@@ -142,7 +142,12 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
     cap_reqs = W.serving_stream(cap_count, float("inf"), seed=1306)
     cap_rep = V.Server(**kw).run(cap_reqs)
     cap = cap_rep.summary()
-    C = cap["requests_per_s"]
+    # Capacity in requests/s: the saturated throughput in site-steps/s over
+    # the mean work of a request of this mix (the mean over a long sample is
+    # steadier than the request count of a short closed-loop run).
+    mix = W.serving_stream(5000, float("inf"), seed=7)
+    mean_work = float(np.mean([r.problem.grid.points() * r.problem.steps for r in mix]))
+    C = cap["site_steps_per_s"] / mean_work
     runs = []
     for i, f in enumerate(rates):
         reqs = W.serving_stream(warm + count, f * C, seed=1306 + 1 + i)
@@ -175,7 +180,8 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
         s.close()
         errs.append(float(np.linalg.norm(x.result.astype(np.complex128) - y) / np.linalg.norm(y)))
     best = max(runs, key=lambda z: z["site_steps_per_s"])
-    return {"workload": "serving_poisson_mixed", "capacity_req_per_s": C, "capacity": cap,
+    return {"workload": "serving_poisson_mixed", "capacity_req_per_s": C, "mean_site_steps_per_request": mean_work,
+            "capacity": cap,
             "runs": runs, "tick_steps": tick, "graph_steps": graph_steps, "budget_gib": budget_gib,
             "per_solve_fp64": {"value": ref_rate, "unit": "site-steps/s",
                                "sample": f"first {ref_count} requests of the closed-loop stream, one after another"},

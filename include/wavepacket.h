@@ -115,7 +115,7 @@ typedef struct {
 
 typedef struct wp_sim wp_sim;
 
-/* Bit mask of wp_observables; the output array holds 8 doubles in this order. */
+/* Bit mask of wp_observables; out[i] belongs to bit i. */
 enum {
   WP_OBS_NORM = 1u << 0,   /* sqrt(<psi|psi>)               (`norm`)          */
   WP_OBS_X = 1u << 1,      /* <psi|x|psi>, not normalised    (`expectation1D`) */
@@ -125,7 +125,13 @@ enum {
   WP_OBS_Y2 = 1u << 5,
   WP_OBS_Z2 = 1u << 6,
   WP_OBS_ENERGY = 1u << 7, /* <psi|K + V(t)|psi>, K spectral (Table 3 energy)  */
-  WP_OBS_ALL = 0xffu
+  WP_OBS_ALL = 0xffu,
+  WP_OBS_SX = 1u << 8,     /* width <x^2> - <x>^2 (Table 3 sx; unnormalised)   */
+  WP_OBS_SY = 1u << 9,
+  WP_OBS_SZ = 1u << 10,
+  WP_OBS_AUTOCORR = 1u << 11, /* |<psi_ref|psi>|^2 (Table 3 autocorrelation);
+                                 needs wp_store_reference                     */
+  WP_OBS_ALL_EXT = 0xfffu
 };
 
 /* Device bytes of the state for this grid (n0*n1*n2 * 8 or 16).
@@ -195,11 +201,29 @@ wp_status wp_set_order(wp_sim *sim, int32_t order);
 wp_status wp_get_state(wp_sim *sim, void *host_out, int32_t as_prec);
 
 /* FP64 observables of the current state at the current time (Table 3 and
- * the `norm` / `expectation1D` utilities of Section 3.2.6): writes the 8
- * values in the WP_OBS_* order into out[8]; entries not in `mask` are 0.
- * Integrals use the rectangle rule over the periodic cell.  Deterministic
- * (fixed reduction order).  Synchronises. */
+ * the `norm` / `expectation1D` utilities of Section 3.2.6): writes out[i]
+ * for bit i of the WP_OBS_* mask, for every i up to the highest bit set
+ * (8 values for masks within WP_OBS_ALL, 12 with the width or
+ * autocorrelation bits); entries not in `mask` are 0.  Integrals use the
+ * rectangle rule over the periodic cell.  Deterministic (fixed reduction
+ * order).  Synchronises.  WP_ESTATE: WP_OBS_AUTOCORR without a stored
+ * reference. */
 wp_status wp_observables(wp_sim *sim, uint32_t mask, double *out);
+
+/* Keep a device copy of the current state as the reference of
+ * WP_OBS_AUTOCORR (the initial wave function the autocorrelation of
+ * Table 3 compares with; Section 3.5 counts its memory).  Allocates one more
+ * state-sized buffer on first use; ordered on the handle's stream. */
+wp_status wp_store_reference(wp_sim *sim);
+
+/* <phi|psi> = sum conj(phi) psi dV over the grid (`integrate3D` of Section
+ * 3.2.6 with f1 = phi, f2 = the current state; the projection onto a
+ * given state of Section 3.2.5).  dev_phi: device memory in the state's
+ * layout, WP_C64 (complex64) or WP_C128 (complex128) per phi_prec,
+ * caller-owned and only read.  out[0], out[1]: real and imaginary part.
+ * FP64 deterministic reduction.  Synchronises.  WP_EINVAL: NULL pointer or
+ * bad precision. */
+wp_status wp_inner(wp_sim *sim, const void *dev_phi, int32_t phi_prec, double *out);
 
 /* Kernel classes of a propagation, for wp_profile_propagate. */
 enum {

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
 #include <string>
@@ -33,12 +34,14 @@ struct wp_sim {
   bool psi_owned = false;
   uint64_t psi_bytes = 0;
   void *scratch = nullptr;  // momentum-space copy for the energy
+  void *ref = nullptr;      // reference state of the autocorrelation
   cx<double> *d_kfull = nullptr, *d_khalf = nullptr;  // n0+n1+n2 entries each
   double *d_k2 = nullptr;                              // k^2 per axis, n0+n1+n2
   cx<double> *d_tw[3] = {nullptr, nullptr, nullptr};
   double *d_partials = nullptr, *d_out8 = nullptr;
   double *d_coef = nullptr;  // waveform values for up to kCoefChunk steps
   cx<double> *d_gauss = nullptr;  // per-axis factors of the last Gaussian state
+  hipEvent_t ev_gauss = nullptr;   // recorded after the kernel that reads d_gauss
   cx<double> *d_wsplit = nullptr;  // split 1D: exp(-2 pi i e/n) as [n2] high and [n1] low factors
   int obs_blocks = 1;
   double t0 = 0.0;
@@ -157,14 +160,44 @@ wp::WaveDev to_dev(const wp_waveform &w) {
   return d;
 }
 
-// Allocate and fill a device array, ordered on `stream`.  Pageable sources
-// are consumed before hipMemcpyAsync returns, so `src` may go out of scope
-// afterwards; no device-wide synchronisation is involved.
+// Tables are copied to the device on a stream of the library's own (one per
+// device, created on first use, kept for the life of the process).  A copy
+// from pageable host memory completes before the call returns; on the
+// caller's stream it would first wait for every kernel queued there, which
+// would stall a caller that creates handles while others compute.
+hipError_t upload_stream(hipStream_t *out) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    it = streams.emplace(dev, st).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+// Copy host data into a device array; complete when this returns.
+hipError_t copy_in(void *dst, const void *src, size_t bytes) {
+  hipStream_t us = nullptr;
+  hipError_t e = upload_stream(&us);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, us);
+  if (e == hipSuccess) e = hipStreamSynchronize(us);
+  return e;
+}
+
+// Allocate and fill a device array (complete when this returns).
 template <class T>
-hipError_t upload(T **dst, const std::vector<T> &src, hipStream_t stream) {
+hipError_t upload(T **dst, const std::vector<T> &src) {
   hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
   if (e != hipSuccess) return e;
-  return hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, stream);
+  return copy_in(*dst, src.data(), sizeof(T) * src.size());
 }
 
 uint64_t table_bytes(const wp_grid_desc &g) {
@@ -175,6 +208,7 @@ uint64_t table_bytes(const wp_grid_desc &g) {
 void release(wp_sim *s) {
   if (s->psi_owned && s->psi) (void)hipFree(s->psi);
   if (s->scratch) (void)hipFree(s->scratch);
+  if (s->ref) (void)hipFree(s->ref);
   if (s->d_kfull) (void)hipFree(s->d_kfull);
   if (s->d_khalf) (void)hipFree(s->d_khalf);
   if (s->d_k2) (void)hipFree(s->d_k2);
@@ -184,6 +218,7 @@ void release(wp_sim *s) {
   if (s->d_out8) (void)hipFree(s->d_out8);
   if (s->d_coef) (void)hipFree(s->d_coef);
   if (s->d_gauss) (void)hipFree(s->d_gauss);
+  if (s->ev_gauss) (void)hipEventDestroy(s->ev_gauss);
   if (s->d_wsplit) (void)hipFree(s->d_wsplit);
 }
 
@@ -324,12 +359,12 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
       k2.push_back(ksq);
     }
   }
-  e = upload(&s->d_kfull, kf, s->stream);
-  if (e == hipSuccess) e = upload(&s->d_khalf, kh, s->stream);
-  if (e == hipSuccess) e = upload(&s->d_k2, k2, s->stream);
+  e = upload(&s->d_kfull, kf);
+  if (e == hipSuccess) e = upload(&s->d_khalf, kh);
+  if (e == hipSuccess) e = upload(&s->d_k2, k2);
   // Line-FFT twiddles per axis, in the stage order the kernels read them.
   for (int d = 0; d < 3 && e == hipSuccess; ++d)
-    e = upload(&s->d_tw[d], stage_twiddles(uint64_t(1) << s->vlg[d]), s->stream);
+    e = upload(&s->d_tw[d], stage_twiddles(uint64_t(1) << s->vlg[d]));
   if (e == hipSuccess && s->split) {
     // exp(-2 pi i e/n), e = q*n1 + r: [n2] factors of q*n1 then [n1] of r.
     const uint64_t n = grid->n[0], n1 = uint64_t(1) << s->vlg[0], n2 = uint64_t(1) << s->vlg[1];
@@ -342,7 +377,7 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
       const double a = -2.0 * kPi * (double)r / (double)n;
       w.push_back({std::cos(a), std::sin(a)});
     }
-    e = upload(&s->d_wsplit, w, s->stream);
+    e = upload(&s->d_wsplit, w);
   }
   if (e == hipSuccess) {
     int64_t b = (s->total + wp::kObsThreads - 1) / wp::kObsThreads;
@@ -449,12 +484,16 @@ wp_status wp_set_state_gaussian(wp_sim *s, const double center[3], const double 
   if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
   if (!s->d_gauss) {
     e = hipMalloc((void **)&s->d_gauss, sizeof(cx<double>) * (s->g.n[0] + s->g.n[1] + s->g.n[2]));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_gauss, hipEventDisableTiming);
     if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
+  } else {
+    // the previous Gaussian kernel must have read the old factors
+    e = hipEventSynchronize(s->ev_gauss);
   }
   cx<double> *d[3] = {s->d_gauss, s->d_gauss + s->g.n[0], s->d_gauss + s->g.n[0] + s->g.n[1]};
-  for (int i = 0; i < 3 && e == hipSuccess; ++i)
-    e = hipMemcpyAsync(d[i], f[i].data(), sizeof(cx<double>) * f[i].size(), hipMemcpyHostToDevice, s->stream);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = copy_in(d[i], f[i].data(), sizeof(cx<double>) * f[i].size());
   if (e == hipSuccess) e = wp::launch_gaussian(storage_prec(s), s->psi, s->gd, d[0], d[1], d[2], s->stream);
+  if (e == hipSuccess) e = hipEventRecord(s->ev_gauss, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "set_state_gaussian");
   s->t0 = t0;
   s->step = 0;
@@ -664,9 +703,50 @@ wp_status wp_get_state(wp_sim *s, void *host_out, int32_t as_prec) {
   return WP_OK;
 }
 
+// <phi|psi> of the current state without the volume element.
+static hipError_t inner_sum(wp_sim *s, const void *phi, int phi_prec, double out2[2]) {
+  double o[8];
+  hipError_t e = wp::launch_inner(phi_prec, phi, storage_prec(s), s->psi, s->total, s->obs_blocks, s->d_partials,
+                                  s->d_out8, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(o, s->d_out8, sizeof(o), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  out2[0] = o[0];
+  out2[1] = o[1];
+  return e;
+}
+
+wp_status wp_store_reference(wp_sim *s) {
+  if (!s) return WP_EINVAL;
+  (void)hipSetDevice(s->device);
+  hipError_t e = ensure_state(s);
+  if (e == hipSuccess && !s->ref) e = hipMalloc(&s->ref, s->psi_bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->ref, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return state_fail(s, e, "store_reference");
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_inner(wp_sim *s, const void *dev_phi, int32_t phi_prec, double *out) {
+  if (!s) return WP_EINVAL;
+  if (!dev_phi || !out) return fail(s, WP_EINVAL, "inner: NULL pointer");
+  if (phi_prec != WP_C64 && phi_prec != WP_C128) return fail(s, WP_EINVAL, "inner: phi_prec must be WP_C64 or WP_C128");
+  (void)hipSetDevice(s->device);
+  hipError_t e = ensure_state(s);
+  double o[2] = {0, 0};
+  if (e == hipSuccess) e = inner_sum(s, dev_phi, phi_prec, o);
+  if (e != hipSuccess) return state_fail(s, e, "inner");
+  double dV = 1.0;
+  for (int d = 0; d < s->g.ndim; ++d) dV *= spacing(s->g, d);
+  out[0] = o[0] * dV;
+  out[1] = o[1] * dV;
+  s->err.clear();
+  return WP_OK;
+}
+
 wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
   if (!s) return WP_EINVAL;
   if (!out) return fail(s, WP_EINVAL, "observables: NULL output");
+  if ((mask & WP_OBS_AUTOCORR) && !s->ref) return fail(s, WP_ESTATE, "observables: no reference state stored");
   (void)hipSetDevice(s->device);
   if (hipError_t e0 = ensure_state(s); e0 != hipSuccess) return state_fail(s, e0, "observables");
   const double t = s->t0 + (double)s->step * s->g.dt;
@@ -716,7 +796,7 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
   }
   if (e == hipErrorNotSupported) return fail(s, WP_EUNSUPPORTED, "observables: energy needs an axis <= 4096 points");
   if (e != hipSuccess) return hip_fail(s, e, "observables");
-  double all[8];
+  double all[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   all[0] = std::sqrt(sums[0] * dV);
   for (int d = 0; d < 3; ++d) {
     all[1 + d] = d < s->g.ndim ? sums[1 + d] * dV : 0.0;
@@ -724,7 +804,18 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
   }
   all[7] = energy ? (s->g.hbar * s->g.hbar / (2.0 * s->g.mass)) * ksum[0] * dV / (double)s->total + sums[7] * dV
                   : 0.0;
-  for (int i = 0; i < 8; ++i) out[i] = (mask & (1u << i)) ? all[i] : 0.0;
+  // widths <x^2> - <x>^2 of Table 3 (from the unnormalised moments)
+  for (int d = 0; d < 3; ++d) all[8 + d] = all[4 + d] - all[1 + d] * all[1 + d];
+  if (mask & WP_OBS_AUTOCORR) {
+    double o[2] = {0, 0};
+    hipError_t e2 = inner_sum(s, s->ref, storage_prec(s), o);
+    if (e2 != hipSuccess) return hip_fail(s, e2, "observables");
+    all[11] = (o[0] * o[0] + o[1] * o[1]) * dV * dV;
+  }
+  int top = 0;
+  for (int i = 0; i < 12; ++i)
+    if (mask & (1u << i)) top = i;
+  for (int i = 0; i <= top; ++i) out[i] = (mask & (1u << i)) ? all[i] : 0.0;
   s->err.clear();
   return WP_OK;
 }
@@ -784,6 +875,12 @@ struct wp_batch {
   // Step counters: [0, count) for the pass schedule (advanced on the device),
   // [count, 2 count) read by the 1D solvers.
   int64_t *d_step = nullptr;
+  // Pinned host mirror of the counters, so that the per-call refresh is an
+  // asynchronous copy; ev_step is recorded after that copy and guards the
+  // mirror against being rewritten before the copy has run.
+  int64_t *h_step = nullptr;
+  hipEvent_t ev_step = nullptr;
+  bool step_pending = false;
   std::vector<PassGroup> groups;
   std::vector<Group1D> groups1d;
   hipGraph_t graph = nullptr;
@@ -813,6 +910,8 @@ void batch_release(wp_batch *b) {
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->side) (void)hipStreamDestroy(b->side);
+  if (b->ev_step) (void)hipEventDestroy(b->ev_step);
+  if (b->h_step) (void)hipHostFree(b->h_step);
   for (void *p : {(void *)b->d_args, (void *)b->d_items, (void *)b->d_args1d, (void *)b->d_pots, (void *)b->d_t0,
                   (void *)b->d_dt, (void *)b->d_coef, (void *)b->d_step})
     if (p) (void)hipFree(p);
@@ -976,6 +1075,8 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     }
   }
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_step, sizeof(int64_t) * 2 * count);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_step, sizeof(int64_t) * 2 * count, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_step, hipEventDisableTiming);
   // The 1D argument blocks read their step from the second set of counters.
   for (size_t j = 0, gi = 0; e == hipSuccess && gi < b->groups1d.size(); ++gi)
     for (int i : members1d[{b->groups1d[gi].prec, b->groups1d[gi].lgN}])
@@ -985,12 +1086,12 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
   }
-  if (e == hipSuccess) e = upload(&b->d_args, args, b->stream);
-  if (e == hipSuccess && !items.empty()) e = upload(&b->d_items, items, b->stream);
-  if (e == hipSuccess && !a1d.empty()) e = upload(&b->d_args1d, a1d, b->stream);
-  if (e == hipSuccess) e = upload(&b->d_pots, pots, b->stream);
-  if (e == hipSuccess) e = upload(&b->d_t0, t0, b->stream);
-  if (e == hipSuccess) e = upload(&b->d_dt, dt, b->stream);
+  if (e == hipSuccess) e = upload(&b->d_args, args);
+  if (e == hipSuccess && !items.empty()) e = upload(&b->d_items, items);
+  if (e == hipSuccess && !a1d.empty()) e = upload(&b->d_args1d, a1d);
+  if (e == hipSuccess) e = upload(&b->d_pots, pots);
+  if (e == hipSuccess) e = upload(&b->d_t0, t0);
+  if (e == hipSuccess) e = upload(&b->d_dt, dt);
   if (e != hipSuccess) {
     batch_release(b);
     delete b;
@@ -1013,10 +1114,12 @@ wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps) {
   (void)hipSetDevice(b->device);
   const int count = (int)b->sims.size();
   // The members' host counters are authoritative: refresh the device copy.
-  std::vector<int64_t> steps(2 * (size_t)count);
-  for (int i = 0; i < count; ++i) steps[i] = steps[count + i] = (int64_t)b->sims[i]->step;
-  hipError_t e = hipMemcpyAsync(b->d_step, steps.data(), sizeof(int64_t) * 2 * count, hipMemcpyHostToDevice,
-                                b->stream);
+  hipError_t e = b->step_pending ? hipEventSynchronize(b->ev_step) : hipSuccess;
+  for (int i = 0; e == hipSuccess && i < count; ++i) b->h_step[i] = b->h_step[count + i] = (int64_t)b->sims[i]->step;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_step, b->h_step, sizeof(int64_t) * 2 * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_step, b->stream);
+  if (e == hipSuccess) b->step_pending = true;
   // 1D members: all steps in one launch per line-length class.
   hipStream_t st1d = b->side ? b->side : b->stream;
   if (e == hipSuccess && b->side) {

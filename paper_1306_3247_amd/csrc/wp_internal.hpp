@@ -115,6 +115,9 @@ hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<doubl
 hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src, int64_t count,
                           hipStream_t s);
 hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s);
+// <phi|psi> without dV: out8[0], out8[1] (precisions 1 = complex64, 2 = complex128).
+hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int blocks,
+                        double *partials, double *out8, hipStream_t s);
 // Waveform values for `count` consecutive steps: out[j*CO_COUNT + w] is
 // waveform w at the time of step T.step + j (plus T.half).
 hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, double *out, hipStream_t s);

@@ -373,6 +373,49 @@ __global__ void __launch_bounds__(kObsThreads) obs_final_kernel(const double *pa
   if (tid < 8) out[tid] = s_red[tid][0];
 }
 
+// <phi|psi>: per-block FP64 partials of conj(phi) psi in the first two of
+// eight slots (the layout obs_final_kernel reduces), same fixed order.
+template <class RP, class RS>
+__global__ void __launch_bounds__(kObsThreads)
+    inner_kernel(const void *phi_, const void *psi_, int64_t total, double *partials) {
+  using TP = typename storage<RP>::type;
+  using TS = typename storage<RS>::type;
+  __shared__ double s_red[2][kObsThreads];
+  const TP *phi = (const TP *)phi_;
+  const TS *psi = (const TS *)psi_;
+  const int tid = threadIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kObsThreads + tid; i < total; i += (int64_t)gridDim.x * kObsThreads) {
+    const double ar = phi[i].x, ai = phi[i].y, br = psi[i].x, bi = psi[i].y;
+    re += ar * br + ai * bi;
+    im += ar * bi - ai * br;
+  }
+  s_red[0][tid] = re;
+  s_red[1][tid] = im;
+  __syncthreads();
+  for (int h = kObsThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      s_red[0][tid] += s_red[0][tid + h];
+      s_red[1][tid] += s_red[1][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid < 8) partials[(int64_t)blockIdx.x * 8 + tid] = tid < 2 ? s_red[tid][0] : 0.0;
+}
+
+hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int blocks,
+                        double *partials, double *out8, hipStream_t s) {
+  const dim3 g(blocks), b(kObsThreads);
+  if (phi_prec == 2 && psi_prec == 2) hipLaunchKernelGGL((inner_kernel<double, double>), g, b, 0, s, phi, psi, total, partials);
+  else if (phi_prec == 2) hipLaunchKernelGGL((inner_kernel<double, float>), g, b, 0, s, phi, psi, total, partials);
+  else if (psi_prec == 2) hipLaunchKernelGGL((inner_kernel<float, double>), g, b, 0, s, phi, psi, total, partials);
+  else hipLaunchKernelGGL((inner_kernel<float, float>), g, b, 0, s, phi, psi, total, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, (const double *)partials, blocks, out8);
+  return hipGetLastError();
+}
+
 hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s) {
   if (prec == 2) hipLaunchKernelGGL(obs_kernel<double>, dim3(blocks), dim3(kObsThreads), 0, s, a);
   else hipLaunchKernelGGL(obs_kernel<float>, dim3(blocks), dim3(kObsThreads), 0, s, a);

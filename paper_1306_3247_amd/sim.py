@@ -23,8 +23,9 @@ V0_KINDS = {"none": 0, "softcore": 1, "morse": 2}
 ORDERS = {"vkv": 0, "kvk": 1}
 STATUS = {0: "WP_OK", -1: "WP_EINVAL", -2: "WP_ENOMEM", -3: "WP_EDEVICE",
           -4: "WP_EUNSUPPORTED", -5: "WP_ESTATE"}
-OBSERVABLES = ("norm", "x", "y", "z", "x2", "y2", "z2", "energy")
+OBSERVABLES = ("norm", "x", "y", "z", "x2", "y2", "z2", "energy", "sx", "sy", "sz", "autocorrelation")
 OBS_ALL = 0xFF
+OBS_ALL_EXT = 0xFFF
 
 
 class WavepacketError(RuntimeError):
@@ -88,6 +89,8 @@ def _load() -> C.CDLL:
         "wp_get_time": [vp, P(d), P(u64)],
         "wp_synchronize": [vp],
         "wp_profile_propagate": [vp, u64, P(d), P(u64)],
+        "wp_store_reference": [vp],
+        "wp_inner": [vp, vp, C.c_int32, P(d)],
         "wp_batch_create": [P(vp), C.c_uint32, vp, P(vp)],
         "wp_batch_set_graph_steps": [vp, C.c_uint32],
         "wp_batch_propagate": [vp, u64],
@@ -243,9 +246,31 @@ class Simulation:
         return out
 
     def observables(self, mask: int = OBS_ALL) -> dict:
-        out = (C.c_double * 8)()
+        out = (C.c_double * 12)()
         self._check(lib.wp_observables(self._h, int(mask), out), "wp_observables")
         return {k: out[i] for i, k in enumerate(OBSERVABLES) if mask & (1 << i)}
+
+    def store_reference(self) -> None:
+        """Keep the current state as the reference of the autocorrelation."""
+        self._check(lib.wp_store_reference(self._h), "wp_store_reference")
+
+    def inner(self, phi) -> complex:
+        """<phi|psi> over the grid; phi is a device tensor (complex64 or
+        complex128, the state's shape) or a host array (copied to the device)."""
+        import torch
+
+        if isinstance(phi, np.ndarray):
+            phi = torch.from_numpy(np.ascontiguousarray(phi)).to("cuda")
+        if phi.dtype not in (torch.complex64, torch.complex128) or not phi.is_cuda:
+            raise ValueError("phi must be a complex64/complex128 CUDA tensor or a numpy array")
+        if phi.numel() != int(np.prod(self.shape)) or not phi.is_contiguous():
+            raise ValueError("phi must be contiguous with the state's size")
+        prec = WP_C128 if phi.dtype == torch.complex128 else WP_C64
+        # the copy above ran on torch's current stream; order the read after it
+        self.stream.wait_stream(torch.cuda.current_stream())
+        out = (C.c_double * 2)()
+        self._check(lib.wp_inner(self._h, C.c_void_p(phi.data_ptr()), prec, out), "wp_inner")
+        return complex(out[0], out[1])
 
     def time(self):
         t, n = C.c_double(), C.c_uint64()

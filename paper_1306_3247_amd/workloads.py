@@ -11,7 +11,8 @@ Workloads (synthetic; the paper measures no public dataset):
   * soft-core 3D atom in a Gaussian-envelope pulse, 512^3 (the throughput
     workload);
   * a batch of 256 independent 2D driven traps with seeded sizes and drives;
-  * a Poisson stream of mixed 1D/2D/3D requests (serving).
+  * a Poisson stream of mixed 1D/2D/3D requests (serving);
+  * the Ba+ ion in a Paul trap of Section 4.2, 512^3 in SI units.
 The Gaussian initial state follows Section 4.2 of the paper.
 """
 from __future__ import annotations
@@ -135,6 +136,35 @@ def driven_trap(ndim: int, n: int, E0: float, omega: float, center, k, steps: in
     p.a[0] = Wave("sin", A0=0.0, A1=-float(E0), omega=float(omega))
     return Problem(f"driven_trap_{ndim}d_{n}", g, p,
                    Gaussian(list(center), [1.0] * ndim, list(k)), steps, precision)
+
+
+# CODATA 2010 values (the paper's constants reference) and the ion of
+# Section 4.2.
+HBAR_SI = 1.054571726e-34     # J s
+E_CHARGE_SI = 1.602176565e-19  # C
+BA138_MASS_SI = 2.28997005e-25  # kg
+
+
+def paul_trap_3d(n: int = 512, steps: int = 18500, precision: str = "c64", half_width: float = 1e-6,
+                 dt: float = 2e-9) -> Problem:
+    """A 138Ba+ ion in a Paul trap (Section 4.2), SI units: V = Z e (U0 + V0
+    cos(Omega t)) (x^2 + y^2 - 2 z^2) / (2 d^2) with Z = 1, U0 = 0, V0 = 200 V,
+    Omega = 2 pi 18 MHz, d^2 = r0^2 + 2 z0^2, r0 = 1.6 mm, z0 = r0/sqrt(2);
+    Gaussian at (2, 1, 2) x 1e-8 m with p = (1e-27, 0, 0) kg m/s and widths
+    (7.342, 7.342, 5.192) x 1e-8 m; n^3 points on [-half_width, half_width)^3
+    (the paper: 512 on [-1e-6, 1e-6) m), dt = 2 ns, 18500 steps."""
+    U0, V0, Omega = 0.0, 200.0, 2.0 * np.pi * 18e6
+    r0 = 1.6e-3
+    z0 = r0 / np.sqrt(2.0)
+    d2 = r0 * r0 + 2.0 * z0 * z0
+    q = 1.0 * E_CHARGE_SI / (2.0 * d2)
+    g = Grid(3, [n] * 3, [-half_width] * 3, [half_width] * 3, mass=BA138_MASS_SI, hbar=HBAR_SI, dt=dt)
+    p = Potential()
+    for d, f in ((0, 1.0), (1, 1.0), (2, -2.0)):
+        p.b[d] = Wave("cos", A0=f * q * U0, A1=f * q * V0, omega=Omega)
+    k = [1e-27 / HBAR_SI, 0.0, 0.0]
+    init = Gaussian([2e-8, 1e-8, 2e-8], [7.342e-8, 7.342e-8, 5.192e-8], k)
+    return Problem(f"paul_trap_3d_{n}", g, p, init, steps, precision)
 
 
 def batch_2d(count: int = 256, seed: int = 1306, steps: int = 1000,

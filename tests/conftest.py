@@ -20,6 +20,18 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def leapfrog(x, p, steps, dt, t0, force, mass=1.0):
+    """Kick (dt/2) at t_n, drift, kick (dt/2) at t_{n+1}; force(x, t)."""
+    xs = [x.copy()]
+    for n in range(steps):
+        tn, tn1 = t0 + n * dt, t0 + (n + 1) * dt
+        p = p + 0.5 * dt * force(x, tn)
+        x = x + dt * p / mass
+        p = p + 0.5 * dt * force(x, tn1)
+        xs.append(x.copy())
+    return np.array(xs)
+
+
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle

@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from conftest import rel_l2
+from conftest import leapfrog, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -124,3 +124,49 @@ def test_modulated_trap_1024_fp32_parity_with_fp64(S, W):
     s.close()
     assert rel_l2(g, r) <= 1e-4
     assert abs(n - 1.0) <= 1e-5
+
+
+def paul_leapfrog(W, prob, steps):
+    d2 = 2 * 1.6e-3 ** 2
+    amp = np.array([1.0, 1.0, -2.0]) * W.E_CHARGE_SI * 200.0 / (2 * d2)
+    omega = 2 * math.pi * 18e6
+    force = lambda x, t: -2 * amp * math.cos(omega * t) * x
+    return leapfrog(np.array(prob.init.center), np.array(prob.init.k) * prob.grid.hbar, steps, prob.grid.dt,
+                    0.0, force, mass=prob.grid.mass)
+
+
+def test_paul_trap_512_fp64_classical(S, W):
+    """Section 4.2 at full size (512^3, SI units), FP64: <x>, <y>, <z> follow
+    the classical kick-drift-kick map every 250 steps for 2000 steps."""
+    prob = W.paul_trap_3d(n=512, steps=2000, precision="c128")
+    xs = paul_leapfrog(W, prob, 2000)
+    s = S.from_problem(prob)
+    for c in range(8):
+        s.propagate(250)
+        o = s.observables(0x0F)
+        want = xs[250 * (c + 1)]
+        got = np.array([o["x"], o["y"], o["z"]])
+        assert np.all(np.abs(got - want) <= 1e-18), (c, got, want)  # metres
+        assert abs(o["norm"] - 1.0) <= 1e-12
+    s.close()
+
+
+def test_paul_trap_512_fp32_full_length(S, W):
+    """Section 4.2 at full size and length (512^3, 18500 steps), FP32 state:
+    the trajectory within 1e-4 of the packet width of the classical map,
+    norm drift <= 1e-5."""
+    prob = W.paul_trap_3d(n=512, steps=18500, precision="c64")
+    xs = paul_leapfrog(W, prob, 18500)
+    s = S.from_problem(prob)
+    worst = 0.0
+    done = 0
+    for n in [1850] * 10:
+        s.propagate(n)
+        done += n
+        o = s.observables(0x0F)
+        err = np.abs(np.array([o["x"], o["y"], o["z"]]) - xs[done])
+        worst = max(worst, float(err.max()))
+    s.close()
+    print(f"Paul trap 512^3 x 18500 FP32: max |<x> - classical| = {worst:.3e} m, norm drift {abs(o['norm'] - 1):.2e}")
+    assert worst <= 1e-4 * 3.7e-8
+    assert abs(o["norm"] - 1.0) <= 1e-5

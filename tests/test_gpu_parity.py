@@ -161,8 +161,15 @@ def test_softcore_3d_scaled(S, W, oracle_mod, precision):
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
-@pytest.mark.parametrize("which", ["1d", "1d_split", "2d", "3d"])
-def test_observables(S, W, oracle_mod, which, precision):
+def test_paul_trap_si_scaled(S, W, oracle_mod, precision):
+    """The Section 4.2 Paul trap (SI units) at the paper's spacing on a 64^3
+    box, 40 steps, every point."""
+    prob = W.paul_trap_3d(n=64, steps=40, precision=precision, half_width=1.25e-7)
+    got, ref, _ = run_both(S, oracle_mod, prob)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+def observable_problem(W, which, precision):
     if which == "1d":
         prob = morse_dipole_1d(W, 1024, 30, precision)
         prob.t0 = 1.0
@@ -175,22 +182,89 @@ def test_observables(S, W, oracle_mod, which, precision):
     else:
         prob = W.softcore_3d(n=32, steps=10, precision=precision, half_width=5.0)
         prob.t0 = 9.0
+    return prob
+
+
+def oracle_all(oracle_mod, prob, psi, t, psi_ref):
+    """Every observable from the oracle: Table 3 widths from its moments,
+    the autocorrelation from its inner product."""
+    ref = oracle_mod.observables(prob.grid, prob.pot, psi, t)
+    for a, m, m2 in (("sx", "x", "x2"), ("sy", "y", "y2"), ("sz", "z", "z2")):
+        ref[a] = ref[m2] - ref[m] ** 2
+    ref["autocorrelation"] = abs(oracle_mod.inner(prob.grid, psi_ref, psi)) ** 2
+    return ref
+
+
+KEYS = ("norm", "x", "y", "z", "x2", "y2", "z2", "energy", "sx", "sy", "sz", "autocorrelation")
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
+@pytest.mark.parametrize("which", ["1d", "1d_split", "2d", "3d"])
+def test_observables_of_oracle_state(S, W, oracle_mod, which, precision):
+    """The reductions alone: the oracle's propagated state is loaded into the
+    handle, with the oracle's initial state as the autocorrelation reference."""
+    prob = observable_problem(W, which, precision)
+    psi0 = oracle_mod.gaussian(prob.grid, prob.init.center, prob.init.sigma, prob.init.k)
+    psi = oracle_mod.propagate(prob.grid, prob.pot, psi0, prob.steps, t0=prob.t0)
+    t = prob.t0 + prob.steps * prob.grid.dt
+    s = S.Simulation(prob.grid, prob.pot, precision)
+    s.set_state(psi0, t0=prob.t0)
+    s.store_reference()
+    s.set_state(psi, t0=t)
+    got = s.observables(S.OBS_ALL_EXT)
+    s.close()
+    ref = oracle_all(oracle_mod, prob, psi, t, psi0)
+    scale = max(1.0, max(abs(v) for v in ref.values()))
+    # FP32 storage rounds the loaded states (relative 6e-8 per value); the
+    # kinetic energy also goes through the FP32 device FFT.
+    tol = 1e-12 if precision == "c128" else 2e-6
+    for k in KEYS:
+        assert abs(got[k] - ref[k]) <= tol * scale, (k, got[k], ref[k])
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
+@pytest.mark.parametrize("which", ["1d", "1d_split", "2d", "3d"])
+def test_observables_after_propagation(S, W, oracle_mod, which, precision):
+    """End to end: device propagation and reductions against the oracle's
+    propagation and reductions (tolerance of the state parity)."""
+    prob = observable_problem(W, which, precision)
     s = S.from_problem(prob)
+    s.store_reference()
     s.propagate(prob.steps)
-    got = s.observables()
-    psi = s.get_state("c128")
+    got = s.observables(S.OBS_ALL_EXT)
     t, n = s.time()
     s.close()
     assert n == prob.steps
     assert t == prob.t0 + prob.steps * prob.grid.dt
-    ref = oracle_mod.observables(prob.grid, prob.pot, psi, t)
+    psi0 = oracle_mod.gaussian(prob.grid, prob.init.center, prob.init.sigma, prob.init.k)
+    psi = oracle_mod.propagate(prob.grid, prob.pot, psi0, prob.steps, t0=prob.t0)
+    ref = oracle_all(oracle_mod, prob, psi, t, psi0)
     scale = max(1.0, max(abs(v) for v in ref.values()))
-    for k in ("norm", "x", "y", "z", "x2", "y2", "z2", "energy"):
-        # The kinetic energy goes through the device FFT, which computes in
-        # the state's precision; everything else is an FP64 sum of the same
-        # values as the oracle's.
-        tol = 1e-6 if (k == "energy" and precision != "c128") else 1e-12
+    tol = 1e-9 if precision == "c128" else 2e-4
+    for k in KEYS:
         assert abs(got[k] - ref[k]) <= tol * scale, (k, got[k], ref[k])
+
+
+@pytest.mark.parametrize("phi_dtype", ["complex64", "complex128"])
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_inner_product(S, W, oracle_mod, precision, phi_dtype):
+    """<phi|psi> with a seeded phi on the device, against the oracle."""
+    import torch
+
+    prob = W.modulated_trap_2d(n=64, steps=0, precision=precision, half_width=8.0)
+    prob.grid.n = [64, 128]
+    psi = W.random_state((64, 128), seed=3)
+    phi = W.random_state((64, 128), seed=4)
+    if phi_dtype == "complex64":
+        phi = phi.astype(np.complex64).astype(np.complex128)
+    if precision == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    s = S.Simulation(prob.grid, prob.pot, precision)
+    s.set_state(psi)
+    got = s.inner(torch.from_numpy(phi.astype(phi_dtype)).cuda())
+    s.close()
+    ref = oracle_mod.inner(prob.grid, phi, psi)
+    assert abs(got - ref) <= 1e-12 * abs(ref) + 1e-13
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])

@@ -14,7 +14,7 @@ import math
 import numpy as np
 import pytest
 
-from conftest import rel_l2
+from conftest import leapfrog, rel_l2
 from paper_1306_3247_amd import workloads as W
 
 # --- discrete Fourier transforms (Section 2.1, eq. ft) -----------------------
@@ -223,18 +223,6 @@ def test_potential_special_values(oracle_mod):
 # --- whole step, quadratic potentials: Ehrenfest = classical leapfrog --------
 
 
-def leapfrog(x, p, steps, dt, t0, force, mass=1.0):
-    """Kick (dt/2) at t_n, drift, kick (dt/2) at t_{n+1}; force(x, t)."""
-    xs = [x.copy()]
-    for n in range(steps):
-        tn, tn1 = t0 + n * dt, t0 + (n + 1) * dt
-        p = p + 0.5 * dt * force(x, tn)
-        x = x + dt * p / mass
-        p = p + 0.5 * dt * force(x, tn1)
-        xs.append(x.copy())
-    return np.array(xs)
-
-
 def test_driven_ho_mean_position_is_classical(oracle_mod):
     """Driven oscillator: for quadratic V each split-step factor maps <x>, <p>
     exactly like the classical kick-drift-kick map."""
@@ -251,6 +239,31 @@ def test_driven_ho_mean_position_is_classical(oracle_mod):
     t = 10.0
     exact = -5 * math.cos(t) + 2.05 * math.sin(t) - 0.05 * t * math.cos(t)
     assert abs(obs["x"] - exact) <= 1e-3
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_paul_trap_axes_follow_classical_leapfrog(oracle_mod, axis):
+    """The Paul trap of Section 4.2 in SI units (phase arguments up to about
+    60 rad per step, hbar ~ 1e-34): the potential and the Gaussian are
+    products over axes, so each axis is a 1D problem, 512 points on
+    [-1e-6, 1e-6) m.  <x> follows the kick-drift-kick map of
+    F = -2 b(t) x, b(t) = (1 or -2) e V0 cos(Omega t) / (2 d^2)."""
+    P = W.paul_trap_3d(n=512)
+    g = W.Grid(1, [512], [-1e-6], [1e-6], mass=P.grid.mass, hbar=P.grid.hbar, dt=P.grid.dt)
+    pot = W.Potential()
+    pot.b[0] = P.pot.b[axis]
+    d2 = 2 * 1.6e-3 ** 2
+    amp = (1.0 if axis < 2 else -2.0) * W.E_CHARGE_SI * 200.0 / (2 * d2)
+    omega = 2 * math.pi * 18e6
+    force = lambda x, t: -2 * amp * math.cos(omega * t) * x
+    c, k = P.init.center[axis], P.init.k[axis]
+    xs = leapfrog(np.array([c]), np.array([k * g.hbar]), 2000, g.dt, 0.0, force, mass=g.mass)
+    psi = oracle_mod.gaussian(g, [c], [P.init.sigma[axis]], [k])
+    for chunk in range(4):
+        psi = oracle_mod.propagate(g, pot, psi, 500, n0=500 * chunk)
+        o = oracle_mod.observables(g, pot, psi, (chunk + 1) * 500 * g.dt)
+        assert abs(o["x"] - xs[500 * (chunk + 1)][0]) <= 1e-19  # metres; |<x>| ~ 1e-8
+        assert abs(o["norm"] - 1.0) <= 1e-12
 
 
 def test_modulated_trap_2d_moments_are_classical(oracle_mod):
@@ -339,6 +352,21 @@ def test_inner_product_of_gaussians(oracle_mod):
     b = oracle_mod.gaussian(g, [0.5], [1.5], [0.0])
     assert oracle_mod.inner(g, a, a) == pytest.approx(1.0, abs=1e-14)
     assert oracle_mod.inner(g, a, b).real == pytest.approx(math.exp(-1.5 ** 2 / (2 * 1.5 ** 2)), abs=1e-13)
+
+
+def test_free_gaussian_autocorrelation_closed_form(oracle_mod):
+    """|<psi(0)|psi(t)>|^2 of a free Gaussian at rest (Table 3 autocorrelation):
+    (1 + (hbar t / (m sigma^2))^2)^(-1/2) for exp(-x^2/sigma^2); the free
+    step is exact in time on the grid."""
+    g = W.Grid(1, [512], [-40.0], [40.0], mass=1.3, hbar=0.8, dt=0.05)
+    pot = W.Potential()
+    sig = 1.5
+    psi0 = oracle_mod.gaussian(g, [0.0], [sig], [0.0])
+    for n in (1, 7, 40):
+        psi = oracle_mod.propagate(g, pot, psi0, n)
+        t = n * g.dt
+        want = (1.0 + (g.hbar * t / (g.mass * sig ** 2)) ** 2) ** -0.5
+        assert abs(oracle_mod.inner(g, psi0, psi)) ** 2 == pytest.approx(want, abs=1e-12)
 
 
 def test_static_potential_energy_conserved(oracle_mod):
