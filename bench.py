@@ -56,11 +56,15 @@ def traffic_for(kind: str, workload: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def time_gpu(sim_mod, prob, precision, steps, warmup):
+def time_gpu(sim_mod, prob, precision, steps, warmup, tune_reps=0):
+    """Time `steps` steps after `warmup`; with tune_reps > 0 the kernel
+    variants are tuned first (before the warm-up, outside the timed region).
+    Returns (handle, ms, wall seconds, tuning timings)."""
     import torch
 
     stream = torch.cuda.current_stream()
     s = sim_mod.from_problem(prob, precision=precision, stream=stream)
+    tuned = s.autotune(tune_reps) if tune_reps > 0 else None
     s.propagate(warmup)
     s.synchronize()
     torch.cuda.synchronize()
@@ -73,10 +77,11 @@ def time_gpu(sim_mod, prob, precision, steps, warmup):
     end.synchronize()
     wall = time.perf_counter() - w0
     torch.cuda.synchronize()
-    return s, start.elapsed_time(end), wall
+    return s, start.elapsed_time(end), wall, tuned
 
 
-def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int, ref_steps: int):
+def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int, ref_steps: int,
+                tune_reps: int = 0):
     """The batched workload: `count` independent 2D driven traps of sizes
     {128, 256, 512}^2 (seeded), FP32 state, advanced together; against the
     same solves advanced one by one with FP64 launches (timed on a sample)."""
@@ -87,6 +92,8 @@ def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int,
     stream = torch.cuda.current_stream()
     sims = [S.from_problem(p, stream=stream) for p in probs]
     b = S.Batch(sims, stream=stream, graph_steps=graph_steps)
+    if tune_reps:
+        b.autotune(tune_reps)  # states are restored
     b.propagate(graph_steps + 1)  # warm-up: graph capture, first replay
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -122,7 +129,8 @@ def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int,
     for p in probs:
         sizes[p.grid.n[0]] = sizes.get(p.grid.n[0], 0) + 1
     return {"workload": f"batch_2d_{count}", "solves": count, "sizes": sizes, "sites": sites, "steps": steps,
-            "graph_steps": graph_steps, "ms": round(ms, 3), "value": sites * steps / (ms / 1e3),
+            "graph_steps": graph_steps, "autotuned": bool(tune_reps), "ms": round(ms, 3),
+            "value": sites * steps / (ms / 1e3),
             "unit": "site-steps/s", "dtype": "f32",
             "per_solve_fp64": {"value": ref_sites * ref_steps / (ms_ref / 1e3), "unit": "site-steps/s",
                                "sample": f"{ref_solves} solves x {ref_steps} steps, one after another"},
@@ -214,6 +222,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=512, help="points per axis")
     ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--pass-reps", type=int, default=20, help="back-to-back launches per timed pass class")
+    ap.add_argument("--no-autotune", action="store_true", help="run the default kernel variants")
+    ap.add_argument("--tune-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -259,7 +270,8 @@ def main() -> int:
     workload = f"softcore_3d_{args.n}"
     sites = prob.grid.points()
 
-    s32, ms32, wall32 = time_gpu(S, prob, "c64", args.steps, args.warmup)
+    tune_reps = 0 if args.no_autotune else args.tune_reps
+    s32, ms32, wall32, tuned32 = time_gpu(S, prob, "c64", args.steps, args.warmup, tune_reps)
     value = sites * args.steps / (ms32 / 1e3)
     out = {"metric": METRIC, "value": value, "unit": "site-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms32 / args.steps, "higher_is_better": True,
@@ -267,10 +279,14 @@ def main() -> int:
            "config": {"workload": workload, "grid": list(prob.grid.shape()), "box": [-40.0, 40.0],
                       "dt": prob.grid.dt, "state": "complex64", "phase_args": "f64"},
            "wall_s_timed": round(wall32, 4)}
+    if tuned32:
+        out["autotune"] = {"reps": tune_reps,
+                           "ms": {c: {str(v): round(m, 4) for v, m in row.items()} for c, row in tuned32.items()},
+                           "chosen": {c: min(row, key=row.get) for c, row in tuned32.items()}}
 
     if not args.no_fp64:
         # Same start, same number of steps, FP64 state: the FP32 error of this run.
-        s64, ms64, _ = time_gpu(S, prob, "c128", args.steps, args.warmup)
+        s64, ms64, _, tuned64 = time_gpu(S, prob, "c128", args.steps, args.warmup, tune_reps)
         b = torch.view_as_real(s64.buffer.view(torch.complex128))
 
         def err(sx):
@@ -281,10 +297,12 @@ def main() -> int:
         rel, drift = err(s32)
         out["fp64"] = {"value": sites * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                        "dtype": "f64"}
+        if tuned64:
+            out["fp64"]["autotune_chosen"] = {c: min(row, key=row.get) for c, row in tuned64.items()}
         out["accuracy"] = {"steps": args.warmup + args.steps, "rel_l2_f32_vs_f64": rel,
                            "norm_drift_f32": drift, "norm_drift_f64": abs(s64.observables(1)["norm"] - 1.0)}
         if args.also_c64x:
-            sx, msx, _ = time_gpu(S, prob, "c64x", args.steps, args.warmup)
+            sx, msx, _, _ = time_gpu(S, prob, "c64x", args.steps, args.warmup)
             relx, driftx = err(sx)
             out["c64x"] = {"value": sites * args.steps / (msx / 1e3), "ms_per_step": msx / args.steps,
                            "dtype": "f64 arithmetic, f32 state", "rel_l2_vs_f64": relx, "norm_drift": driftx,
@@ -294,17 +312,24 @@ def main() -> int:
 
     # Roofline of the dominant kernel: every pass reads and writes the whole
     # state once, so its algorithmic bytes per launch are 2 * state bytes.
+    # Each steady-step pass class is timed over back-to-back launches between
+    # one event pair on the handle's stream (an event pair around every
+    # launch, as in the per-step breakdown below, adds its own delay to each
+    # launch); the class with the longest launch dominates a step.
     prof = s32.profile_propagate(args.profile_steps)
-    kind, (cnt, tot) = max(prof.items(), key=lambda kv: kv[1][1])
     state_bytes = S.state_bytes(prob.grid, "c64")
     alg_bytes = 2 * state_bytes
-    avg_ms = tot / cnt
+    timed = {k: s32.time_pass(k, args.pass_reps) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
+    kind, avg_ms = max(timed.items(), key=lambda kv: kv[1])
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": f"pass:{kind}", "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": traffic_for(kind, workload), "avg_launch_ms": round(avg_ms, 4),
-                       "alg_bytes_per_launch": alg_bytes,
-                       "passes": {k: {"launches": c, "avg_ms": round(m / c, 4)} for k, (c, m) in prof.items()}}
+                       "alg_bytes_per_launch": alg_bytes, "reps": args.pass_reps,
+                       "passes": {k: {"avg_ms": round(m, 4),
+                                      "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)} for k, m in timed.items()},
+                       "passes_event_per_launch": {k: {"launches": c, "avg_ms": round(m / c, 4)}
+                                                   for k, (c, m) in prof.items()}}
     # Whole-step view against the 4-pass byte model (64 B per site-step).
     step_gbs = 4 * alg_bytes * args.steps / (ms32 / 1e3) / 1e9
     out["step_roofline"] = {"model": "4 passes x (read+write) per step", "achieved": round(step_gbs, 1),
@@ -312,7 +337,8 @@ def main() -> int:
     s32.close()
     torch.cuda.synchronize()
     if not args.no_batch:
-        out["batch"] = batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200)
+        out["batch"] = batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200,
+                                   tune_reps)
     if not args.no_serve:
         from paper_1306_3247_amd import serve as V
 

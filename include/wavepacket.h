@@ -246,6 +246,51 @@ enum {
  * in 1..100000 (WP_EINVAL otherwise). */
 wp_status wp_profile_propagate(wp_sim *sim, uint64_t nsteps, double *ms, uint64_t *count);
 
+/* Device time of one line-pass class of a 2D/3D (or split 1D) step: the
+ * pass of class `kind` (WP_PASS_AXIS0, _MID_FWD, _LAST, _MID_INV or _EDGE,
+ * as launched by wp_propagate at the current step) is launched `reps` times
+ * back to back on the handle's stream between one event pair; *ms receives
+ * the average per launch.  Measurement only: the state is transformed
+ * `reps` times and is not a solution afterwards (the step counter is
+ * unchanged).  Synchronises.  WP_EINVAL: reps not in 1..10000, a kind the
+ * grid does not have (e.g. a middle axis in 2D, any pass of a 1D grid
+ * solved in one workgroup). */
+wp_status wp_time_pass(wp_sim *sim, int32_t kind, uint32_t reps, double *ms);
+
+/* ---- Autotuner -------------------------------------------------------
+ * Every line pass exists in up to WP_TUNE_VARIANTS compiled shapes
+ * (variant bit 0: 8 instead of 16 values per thread in FP32 passes; bit 1:
+ * 256-thread workgroups, three per CU, instead of 512-thread ones, two per
+ * CU; variants beyond 0 exist for line lengths 64..1024 and pass kinds F,
+ * V, K; FP64 passes have variants 0 and 2).  A process-wide table holds the
+ * variant per (batched, precision, log2 line length, strided layout, pass
+ * kind: 0 FFT, 1 potential, 2 kinetic, 3/4 split 1D potential/kinetic);
+ * entries never tuned run variant 0.  Results do not depend on the variant
+ * (the same arithmetic in the same order), only the speed does. */
+#define WP_TUNE_VARIANTS 4
+
+/* Time every variant of the handle's line passes ([0] potential pass of the
+ * first axis, [1] middle-axis FFT (3D), [2] kinetic pass of the last axis)
+ * over `reps` back-to-back launches each, on a device copy of the state
+ * (the state itself is unchanged; one state-sized scratch buffer is
+ * allocated on first use), and store the fastest in the table.  ms, if not
+ * NULL, receives 3 x WP_TUNE_VARIANTS average milliseconds (NaN for
+ * variants not tried).  Passes built afterwards by any handle use the
+ * table; a 1D grid solved in one workgroup has nothing to tune (WP_OK).
+ * Synchronises.  WP_EINVAL: reps not in 1..10000. */
+wp_status wp_autotune(wp_sim *sim, uint32_t reps, double *ms);
+
+/* The table entry for one pass shape (see above); *tune receives 0 for
+ * shapes never tuned. */
+wp_status wp_tune_get(int32_t batched, int32_t prec, int32_t lg_n, int32_t strided, int32_t kind,
+                      int32_t *tune);
+/* Set a table entry (for example from a saved tuning run).  WP_EINVAL for
+ * a value out of range.  Takes effect for passes built afterwards. */
+wp_status wp_tune_set(int32_t batched, int32_t prec, int32_t lg_n, int32_t strided, int32_t kind,
+                      int32_t tune);
+/* Forget every table entry. */
+void wp_tune_clear(void);
+
 /* ---- batches: many independent solves advanced together -------------- */
 
 typedef struct wp_batch wp_batch;
@@ -276,6 +321,16 @@ wp_status wp_batch_set_graph_steps(wp_batch *b, uint32_t k);
  * member's state, step counter and time advance exactly as with
  * wp_propagate(member, nsteps), bit for bit. */
 wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps);
+
+/* Tune the batched kernels: every pass group of the batch (same
+ * precision, line length, layout and kind) is timed in each variant over
+ * `reps` back-to-back launches on the members' states, which are saved to
+ * per-member scratch buffers (allocated on first use) and restored; the
+ * fastest variants go into the table (batched entries) and the batch's
+ * block maps are rebuilt for them (a captured graph is captured again at
+ * the next propagation).  Synchronises the batch's stream.  WP_EINVAL: reps
+ * not in 1..10000. */
+wp_status wp_batch_autotune(wp_batch *b, uint32_t reps);
 
 /* Release the batch's own device buffers and graphs (members untouched).
  * Waits for the batch's stream. */

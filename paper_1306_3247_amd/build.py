@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwavepacket.so")
 
-SOURCES = ["wp_kernels.hip", "wp_pass_c64.hip", "wp_pass_c64x.hip", "wp_pass_c128.hip", "wp_capi.cpp"]
+SOURCES = ["wp_kernels.hip", "wp_pass_c64.hip", "wp_pass_c64_t1.hip", "wp_pass_c64_t2.hip", "wp_pass_c64_t3.hip",
+           "wp_pass_c64x.hip", "wp_pass_c128.hip", "wp_pass_c128_t2.hip", "wp_capi.cpp"]
 
 # Packed FP32 instructions are kept out of every kernel: ordinary float code
 # compiled with them enabled has produced silent wrong results on this chip.
@@ -28,7 +29,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every source to an object, then link the shared library."""
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)

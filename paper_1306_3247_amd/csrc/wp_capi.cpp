@@ -242,6 +242,37 @@ wp_status state_fail(wp_sim *s, hipError_t e, const char *what) {
                                   : hip_fail(s, e, what);
 }
 
+// Tuning table: the kernel variant chosen per (batched, precision, line
+// length, layout, pass kind), filled by the autotuner or by wp_tune_set;
+// absent entries run variant 0.  Shared by every handle in the process.
+struct TuneKey {
+  int batched, prec, lgN, strided, kind;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(batched, prec, lgN, strided, kind) < std::tie(o.batched, o.prec, o.lgN, o.strided, o.kind);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+int tune_for(int batched, int prec, int lgN, bool strided, int kind) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find({batched, prec, lgN, strided ? 1 : 0, kind});
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void tune_store(int batched, int prec, int lgN, bool strided, int kind, int tune) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[{batched, prec, lgN, strided ? 1 : 0, kind}] = tune;
+}
+
+// Pass kind (wp::PK_*) of a set of operations on an axis of a handle.
+int kind_of(const wp_sim *s, int axis, uint32_t ops) {
+  if (s->split && (axis == 0 || (ops & wp::OP_K))) return axis == 0 ? 3 : 4;
+  if (ops & wp::OP_V) return 1;
+  if (ops & wp::OP_K) return 2;
+  return 0;
+}
+
 wp::PassArgs pass_args(const wp_sim *s, int axis, uint32_t ops) {
   wp::PassArgs a{};
   a.psi = s->psi;
@@ -267,6 +298,7 @@ wp::PassArgs pass_args(const wp_sim *s, int axis, uint32_t ops) {
     off += (int)s->g.n[d];
   }
   a.tw = s->d_tw[axis];
+  a.tune = tune_for(0, s->prec, s->vlg[axis], lgi > 0, kind_of(s, axis, ops));
   return a;
 }
 
@@ -673,6 +705,117 @@ wp_status wp_profile_propagate(wp_sim *s, uint64_t nsteps, double *ms, uint64_t 
   return WP_OK;
 }
 
+// Average device time of `reps` back-to-back launches of one pass (after one
+// warm-up launch), between one event pair on the handle's stream.
+static hipError_t time_launches(wp_sim *s, const wp::PassArgs &a, uint32_t reps, double *ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = wp::launch_pass(s->prec, a, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+  for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = wp::launch_pass(s->prec, a, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float m = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e == hipSuccess) *ms = (double)m / reps;
+  return e;
+}
+
+// Coefficient row for the current step, for timing potential passes.
+static hipError_t current_coef(wp_sim *s, wp::PassArgs &a) {
+  wp::TimeDev T{};
+  T.t0 = s->t0;
+  T.dt = s->g.dt;
+  T.step = (int64_t)s->step;
+  a.coef = s->d_coef;
+  return wp::launch_coefficients(s->pd, T, 1, s->d_coef, s->stream);
+}
+
+wp_status wp_time_pass(wp_sim *s, int32_t kind, uint32_t reps, double *ms) {
+  if (!s) return WP_EINVAL;
+  if (!ms) return fail(s, WP_EINVAL, "time_pass: NULL output");
+  if (reps < 1 || reps > 10000) return fail(s, WP_EINVAL, "time_pass: reps must be in 1..10000");
+  if (s->g.ndim == 1 && !s->split) return fail(s, WP_EINVAL, "time_pass: 1D grids up to 8192 points have no line passes");
+  const int last = s->vdim - 1;
+  if ((kind == WP_PASS_MID_FWD || kind == WP_PASS_MID_INV) && s->vdim != 3)
+    return fail(s, WP_EINVAL, "time_pass: middle-axis passes exist only in 3D");
+  wp::PassArgs a{};
+  switch (kind) {
+    case WP_PASS_AXIS0:
+      a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | wp::OP_FWD);
+      a.vtau = s->g.dt / s->g.hbar;
+      break;
+    case WP_PASS_EDGE:
+      a = pass_args(s, 0, wp::OP_V | wp::OP_FWD);
+      a.vtau = 0.5 * s->g.dt / s->g.hbar;
+      break;
+    case WP_PASS_MID_FWD: a = pass_args(s, 1, wp::OP_FWD); break;
+    case WP_PASS_MID_INV: a = pass_args(s, 1, wp::OP_PRE_INV); break;
+    case WP_PASS_LAST: a = pass_args(s, last, wp::OP_FWD | wp::OP_K | wp::OP_POST_INV); break;
+    default: return fail(s, WP_EINVAL, "time_pass: unknown pass kind");
+  }
+  (void)hipSetDevice(s->device);
+  hipError_t e = ensure_state(s);
+  a.psi = s->psi;
+  if (e == hipSuccess && (a.ops & wp::OP_V)) e = current_coef(s, a);
+  if (e == hipSuccess) e = time_launches(s, a, reps, ms);
+  if (e != hipSuccess) return hip_fail(s, e, "time_pass");
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
+  if (!s) return WP_EINVAL;
+  if (reps < 1 || reps > 10000) return fail(s, WP_EINVAL, "autotune: reps must be in 1..10000");
+  if (ms)
+    for (int i = 0; i < 3 * wp::kTuneSlots; ++i) ms[i] = NAN;
+  if (s->g.ndim == 1 && !s->split) {
+    s->err.clear();
+    return WP_OK;  // one workgroup solves the whole 1D grid: nothing to tune
+  }
+  (void)hipSetDevice(s->device);
+  hipError_t e = ensure_state(s);
+  // The candidates run on a copy of the state, which they transform.
+  if (e == hipSuccess && !s->scratch) e = hipMalloc(&s->scratch, s->psi_bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
+  const int last = s->vdim - 1;
+  struct Cls {
+    int axis;
+    uint32_t ops;
+  } cls[3] = {{0, wp::OP_PRE_INV | wp::OP_V | wp::OP_FWD}, {1, wp::OP_FWD}, {last, wp::OP_FWD | wp::OP_K | wp::OP_POST_INV}};
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    if (c == 1 && s->vdim != 3) continue;
+    wp::PassArgs a = pass_args(s, cls[c].axis, cls[c].ops);
+    a.psi = s->scratch;
+    a.vtau = s->g.dt / s->g.hbar;
+    if (a.ops & wp::OP_V) e = current_coef(s, a);
+    const int kind = kind_of(s, cls[c].axis, cls[c].ops);
+    const int lgN = s->vlg[cls[c].axis];
+    int cand[4];
+    const int nc = wp::tune_candidates(s->prec, lgN, kind, cand);
+    int best = 0;
+    double best_ms = 0.0;
+    for (int i = 0; i < nc && e == hipSuccess; ++i) {
+      a.tune = cand[i];
+      double m = 0.0;
+      e = time_launches(s, a, reps, &m);
+      if (e != hipSuccess) break;
+      if (ms) ms[c * wp::kTuneSlots + cand[i]] = m;
+      if (i == 0 || m < best_ms) {
+        best = cand[i];
+        best_ms = m;
+      }
+    }
+    if (e == hipSuccess) tune_store(0, s->prec, lgN, a.lg_inner > 0, kind, best);
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "autotune");
+  s->err.clear();
+  return WP_OK;
+}
+
 wp_status wp_get_state(wp_sim *s, void *host_out, int32_t as_prec) {
   if (!s) return WP_EINVAL;
   if (!host_out) return fail(s, WP_EINVAL, "get_state: NULL host buffer");
@@ -853,6 +996,14 @@ struct PassGroup {
   int slot, prec, lgN, kind;
   bool strided;
   uint32_t item_off, nblocks;
+  int tune;
+};
+// The solves of one pass group and their line counts (the block map is
+// rebuilt from this when the group's kernel variant changes).
+struct GroupSpec {
+  int slot, prec, lgN, kind;
+  bool strided;
+  std::vector<std::pair<int, int64_t>> members;  // (solve, lines)
 };
 struct Group1D {
   int prec, lgN;
@@ -882,6 +1033,7 @@ struct wp_batch {
   hipEvent_t ev_step = nullptr;
   bool step_pending = false;
   std::vector<PassGroup> groups;
+  std::vector<GroupSpec> specs;
   std::vector<Group1D> groups1d;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -936,10 +1088,30 @@ hipError_t run_slot(wp_batch *b, hipStream_t st, int slot, int var, int row) {
     L.lgN = g.lgN;
     L.strided = g.strided;
     L.kind = g.kind;
+    L.tune = g.tune;
     hipError_t r = wp::launch_batch_pass(g.prec, L, st);
     if (r != hipSuccess) return r;
   }
   return hipSuccess;
+}
+
+// Block maps of all pass groups from the group specs and the tuning table:
+// one item per (solve, tile), tiles sized for each group's variant.
+std::vector<wp::BatchItem> build_items(wp_batch *b) {
+  std::vector<wp::BatchItem> items;
+  b->groups.clear();
+  for (const GroupSpec &sp : b->specs) {
+    const int tune = wp::effective_tune(sp.prec, sp.lgN, sp.kind, tune_for(1, sp.prec, sp.lgN, sp.strided, sp.kind));
+    const int tile = wp::pass_tile(sp.prec, sp.lgN, sp.strided, sp.kind, tune);
+    PassGroup g{sp.slot, sp.prec, sp.lgN, sp.kind, sp.strided, (uint32_t)items.size(), 0, tune};
+    for (auto &m : sp.members) {
+      const int64_t tiles = (m.second + tile - 1) / tile;
+      for (int64_t t = 0; t < tiles; ++t) items.push_back({m.first, (int32_t)t});
+    }
+    g.nblocks = (uint32_t)(items.size() - g.item_off);
+    b->groups.push_back(g);
+  }
+  return items;
 }
 
 hipError_t refresh_coef(wp_batch *b, hipStream_t st, int rows) {
@@ -996,7 +1168,7 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
       return std::tie(slot, prec, lgN, kind, strided) < std::tie(o.slot, o.prec, o.lgN, o.kind, o.strided);
     }
   };
-  std::map<Key, std::vector<std::pair<int, int64_t>>> members;  // (solve, tiles)
+  std::map<Key, std::vector<std::pair<int, int64_t>>> members;  // (solve, lines)
   std::map<std::pair<int, int>, std::vector<int>> members1d;    // (prec, lgN) -> solves
   if (e == hipSuccess) {
     e = hipMalloc((void **)&b->d_coef, sizeof(double) * wp::CO_COUNT * (size_t)b->rows * count);
@@ -1030,9 +1202,7 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     auto add = [&](int slot, int axis, int kind) {
       const wp::PassArgs &pa = A[slot == SLOT_V ? V_FIRST : slot == SLOT_K ? K_LAST : slot == SLOT_FFWD ? F_FWD : F_INV];
       const bool strided = pa.lg_inner > 0;
-      const int tile = wp::pass_tile(s->prec, s->vlg[axis], strided, kind);
-      const int64_t tiles = (pa.n_lines + tile - 1) / tile;
-      members[{slot, s->prec, s->vlg[axis], kind, strided}].push_back({(int)i, tiles});
+      members[{slot, s->prec, s->vlg[axis], kind, strided}].push_back({(int)i, pa.n_lines});
     };
     add(SLOT_V, 0, s->split ? 3 : 1);
     add(SLOT_K, last, s->split ? 4 : 2);
@@ -1042,14 +1212,9 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     }
   }
   if (e == hipSuccess) {
-    for (auto &kv : members) {
-      PassGroup g{kv.first.slot, kv.first.prec, kv.first.lgN, kv.first.kind, kv.first.strided,
-                  (uint32_t)items.size(), 0};
-      for (auto &m : kv.second)
-        for (int64_t t = 0; t < m.second; ++t) items.push_back({m.first, (int32_t)t});
-      g.nblocks = (uint32_t)(items.size() - g.item_off);
-      b->groups.push_back(g);
-    }
+    for (auto &kv : members)
+      b->specs.push_back({kv.first.slot, kv.first.prec, kv.first.lgN, kv.first.kind, kv.first.strided, kv.second});
+    items = build_items(b);
     for (auto &kv : members1d) {
       Group1D g{kv.first.first, kv.first.second, (uint32_t)a1d.size(), (uint32_t)kv.second.size()};
       for (int i : kv.second) {
@@ -1188,6 +1353,120 @@ wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps) {
   for (wp_sim *s : b->sims) s->step += nsteps;
   b->err.clear();
   return WP_OK;
+}
+
+wp_status wp_batch_autotune(wp_batch *b, uint32_t reps) {
+  if (!b) return WP_EINVAL;
+  if (reps < 1 || reps > 10000) return bfail(b, WP_EINVAL, "batch_autotune: reps must be in 1..10000");
+  if (b->specs.empty()) {
+    b->err.clear();
+    return WP_OK;
+  }
+  (void)hipSetDevice(b->device);
+  const int count = (int)b->sims.size();
+  hipError_t e = hipStreamSynchronize(b->stream);
+  // The candidates transform the members' states in place: save and restore.
+  std::vector<char> saved(count, 0);
+  for (const GroupSpec &sp : b->specs)
+    for (auto &m : sp.members) saved[m.first] = 1;
+  for (int i = 0; i < count && e == hipSuccess; ++i) {
+    if (!saved[i]) continue;
+    wp_sim *s = b->sims[i];
+    if (!s->scratch) e = hipMalloc(&s->scratch, s->psi_bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, b->stream);
+  }
+  // Waveform rows for the members' current steps (potential passes read row 0).
+  for (int i = 0; i < count && e == hipSuccess; ++i) b->h_step[i] = b->h_step[count + i] = (int64_t)b->sims[i]->step;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_step, b->h_step, sizeof(int64_t) * 2 * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = refresh_coef(b, b->stream, 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  b->step_pending = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (const GroupSpec &sp : b->specs) {
+    if (e != hipSuccess) break;
+    const int var = sp.slot == SLOT_V ? V_STEADY : sp.slot == SLOT_K ? K_LAST : sp.slot == SLOT_FFWD ? F_FWD : F_INV;
+    int cand[4];
+    const int nc = wp::tune_candidates(sp.prec, sp.lgN, sp.kind, cand);
+    if (nc < 2) continue;
+    int best = 0;
+    double best_ms = 0.0;
+    for (int c = 0; c < nc && e == hipSuccess; ++c) {
+      const int tile = wp::pass_tile(sp.prec, sp.lgN, sp.strided, sp.kind, cand[c]);
+      std::vector<wp::BatchItem> items;
+      for (auto &m : sp.members)
+        for (int64_t t = 0; t < (m.second + tile - 1) / tile; ++t) items.push_back({m.first, (int32_t)t});
+      wp::BatchItem *d_items = nullptr;
+      e = upload(&d_items, items);
+      wp::BatchLaunch L{};
+      L.args = b->d_args;
+      L.items = d_items;
+      L.nblocks = (int)items.size();
+      L.nvar = kVariants;
+      L.var = var;
+      L.row = 0;
+      L.lgN = sp.lgN;
+      L.strided = sp.strided;
+      L.kind = sp.kind;
+      L.tune = cand[c];
+      if (e == hipSuccess) e = wp::launch_batch_pass(sp.prec, L, b->stream);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+      for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = wp::launch_batch_pass(sp.prec, L, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float m = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
+      if (d_items) (void)hipFree(d_items);
+      if (e == hipSuccess && (c == 0 || m < best_ms)) {
+        best = cand[c];
+        best_ms = m;
+      }
+    }
+    if (e == hipSuccess) tune_store(1, sp.prec, sp.lgN, sp.strided, sp.kind, best);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (int i = 0; i < count && e == hipSuccess; ++i)
+    if (saved[i])
+      e = hipMemcpyAsync(b->sims[i]->psi, b->sims[i]->scratch, b->sims[i]->psi_bytes, hipMemcpyDeviceToDevice,
+                         b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  // New block maps for the chosen variants; the captured graph is stale.
+  if (e == hipSuccess) {
+    std::vector<wp::BatchItem> items = build_items(b);
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_items = nullptr;
+    if (!items.empty()) e = upload(&b->d_items, items);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->exec_steps = 0;
+  }
+  if (e != hipSuccess) return bfail(b, WP_EDEVICE, std::string("batch_autotune: ") + hipGetErrorString(e));
+  b->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_tune_get(int32_t batched, int32_t prec, int32_t lg_n, int32_t strided, int32_t kind, int32_t *tune) {
+  if (!tune) return WP_EINVAL;
+  *tune = tune_for(batched ? 1 : 0, prec, lg_n, strided != 0, kind);
+  return WP_OK;
+}
+
+wp_status wp_tune_set(int32_t batched, int32_t prec, int32_t lg_n, int32_t strided, int32_t kind, int32_t tune) {
+  if (prec < WP_C64 || prec > WP_C64X || lg_n < 1 || lg_n > 12 || kind < 0 || kind > 4 || tune < 0 ||
+      tune >= wp::kTuneSlots)
+    return WP_EINVAL;
+  tune_store(batched ? 1 : 0, prec, lg_n, strided != 0, kind, tune);
+  return WP_OK;
+}
+
+void wp_tune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
 }
 
 wp_status wp_batch_destroy(wp_batch *b) {

@@ -58,6 +58,7 @@ struct PassArgs {
   // for 0 <= e < n = 2^g.lg[0]; split_h = log2 n1.
   const cx<double> *wsplit[2];
   int32_t split_h;
+  int32_t tune;  // kernel variant (see pass_cfg); 0 = default
 };
 
 struct Solve1DArgs {
@@ -105,6 +106,7 @@ struct BatchLaunch {
   int lgN;
   bool strided;
   int kind;  // 0 FFT only, 1 potential, 2 kinetic, 3 / 4 split 1D potential / kinetic
+  int tune;  // kernel variant
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -133,7 +135,15 @@ constexpr int kCoefChunk = 1024;  // steps per coefficient table
 
 bool pass_supported(int prec, int lgN);
 hipError_t launch_batch_pass(int prec, const BatchLaunch &b, hipStream_t s);
-int pass_tile(int prec, int lgN, bool strided, int kind);
+// Lines per workgroup of the variant that launch_*pass runs for `tune`.
+int pass_tile(int prec, int lgN, bool strided, int kind, int tune);
+// The variant actually run for a requested one (variants are compiled for
+// some precisions, lengths and kinds only; elsewhere 0 runs).
+int effective_tune(int prec, int lgN, int kind, int tune);
+// Variants of a line pass (the tuning table's values are 0..kTuneSlots-1).
+constexpr int kTuneSlots = 4;
+// Distinct variants worth trying for a precision, line length and kind.
+int tune_candidates(int prec, int lgN, int kind, int *out4);
 // 1D solves in one launch, one workgroup each (all of line length 2^lgN).
 hipError_t launch_solve1d_batch(int prec, int lgN, const Solve1DArgs *args, int count, int64_t nsteps,
                                 hipStream_t s);

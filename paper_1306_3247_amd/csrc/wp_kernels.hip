@@ -5,44 +5,84 @@
 // reads every line along one axis from HBM once, does all of its work in
 // registers and LDS (inverse FFT, potential phase, forward FFT, kinetic
 // phase, ...) and writes the line back once.
-#include "wp_internal.hpp"
+#include "wp_pass.hpp"
 
 namespace wp {
 
-hipError_t dispatch_pass_c64(int lgN, const PassArgs &a, hipStream_t s);
-hipError_t dispatch_pass_c64x(int lgN, const PassArgs &a, hipStream_t s);
-hipError_t dispatch_pass_c128(int lgN, const PassArgs &a, hipStream_t s);
-hipError_t dispatch_batch_c64(const BatchLaunch &b, hipStream_t s);
-hipError_t dispatch_batch_c64x(const BatchLaunch &b, hipStream_t s);
-hipError_t dispatch_batch_c128(const BatchLaunch &b, hipStream_t s);
-int pass_tile_c64(int lgN, bool strided, int kind);
-int pass_tile_c64x(int lgN, bool strided, int kind);
-int pass_tile_c128(int lgN, bool strided, int kind);
-
-hipError_t launch_batch_pass(int prec, const BatchLaunch &b, hipStream_t s) {
-  if (!pass_supported(prec, b.lgN) || b.nblocks <= 0) return hipErrorInvalidValue;
-  if (prec == 2) return dispatch_batch_c128(b, s);
-  if (prec == 3) return dispatch_batch_c64x(b, s);
-  return dispatch_batch_c64(b, s);
-}
-
-int pass_tile(int prec, int lgN, bool strided, int kind) {
-  if (prec == 2) return pass_tile_c128(lgN, strided, kind);
-  if (prec == 3) return pass_tile_c64x(lgN, strided, kind);
-  return pass_tile_c64(lgN, strided, kind);
-}
+#define WP_DECLARE_VARIANT(P, T)                                              \
+  hipError_t dispatch_pass_##P##_##T(int lgN, const PassArgs &a, hipStream_t s); \
+  hipError_t dispatch_batch_##P##_##T(const BatchLaunch &b, hipStream_t s);     \
+  int pass_tile_##P##_##T(int lgN, bool strided, int kind);
+WP_DECLARE_VARIANT(c64, 0)
+WP_DECLARE_VARIANT(c64, 1)
+WP_DECLARE_VARIANT(c64, 2)
+WP_DECLARE_VARIANT(c64, 3)
+WP_DECLARE_VARIANT(c128, 0)
+WP_DECLARE_VARIANT(c128, 2)
+WP_DECLARE_VARIANT(c64x, 0)
+#undef WP_DECLARE_VARIANT
 
 bool pass_supported(int prec, int lgN) { return prec >= 1 && prec <= 3 && lgN >= 1 && lgN <= 12; }
 
+int effective_tune(int prec, int lgN, int kind, int tune) {
+  if (kind > 2 || lgN < 6 || lgN > 10 || tune < 0) return 0;
+  if (prec == 1) return tune & 3;
+  if (prec == 2) return tune & 2;
+  return 0;
+}
+
+int tune_candidates(int prec, int lgN, int kind, int *out4) {
+  int n = 0;
+  for (int t = 0; t < 4; ++t)
+    if (effective_tune(prec, lgN, kind, t) == t) out4[n++] = t;
+  return n;
+}
+
+// Line length of a pass: the axis length, or on a split 1D grid n1 =
+// 2^split_h (axis 0) and n2 = n/n1 (axis 1).
+static int pass_lgN(const PassArgs &a) {
+  return a.split_h > 0 ? (a.axis == 0 ? a.split_h : a.g.lg[0] - a.split_h) : a.g.lg[a.axis];
+}
+
 hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s) {
-  // Line length: the axis length, or on a split 1D grid n1 = 2^split_h
-  // (axis 0) and n2 = n/n1 (axis 1).
-  const int lgN = a.split_h > 0 ? (a.axis == 0 ? a.split_h : a.g.lg[0] - a.split_h) : a.g.lg[a.axis];
+  const int lgN = pass_lgN(a);
   if (!pass_supported(prec, lgN)) return hipErrorInvalidValue;
   if ((a.ops & OP_V) && (a.ops & OP_K)) return hipErrorInvalidValue;
-  if (prec == 2) return dispatch_pass_c128(lgN, a, s);
-  if (prec == 3) return dispatch_pass_c64x(lgN, a, s);
-  return dispatch_pass_c64(lgN, a, s);
+  const int t = effective_tune(prec, lgN, pass_kind_of(a), a.tune);
+  if (prec == 2) return t ? dispatch_pass_c128_2(lgN, a, s) : dispatch_pass_c128_0(lgN, a, s);
+  if (prec == 3) return dispatch_pass_c64x_0(lgN, a, s);
+  switch (t) {
+    case 1: return dispatch_pass_c64_1(lgN, a, s);
+    case 2: return dispatch_pass_c64_2(lgN, a, s);
+    case 3: return dispatch_pass_c64_3(lgN, a, s);
+    default: return dispatch_pass_c64_0(lgN, a, s);
+  }
+}
+
+hipError_t launch_batch_pass(int prec, const BatchLaunch &b, hipStream_t s) {
+  if (!pass_supported(prec, b.lgN) || b.nblocks <= 0) return hipErrorInvalidValue;
+  const int t = effective_tune(prec, b.lgN, b.kind, b.tune);
+  if (prec == 2) return t ? dispatch_batch_c128_2(b, s) : dispatch_batch_c128_0(b, s);
+  if (prec == 3) return dispatch_batch_c64x_0(b, s);
+  switch (t) {
+    case 1: return dispatch_batch_c64_1(b, s);
+    case 2: return dispatch_batch_c64_2(b, s);
+    case 3: return dispatch_batch_c64_3(b, s);
+    default: return dispatch_batch_c64_0(b, s);
+  }
+}
+
+int pass_tile(int prec, int lgN, bool strided, int kind, int tune) {
+  if (!pass_supported(prec, lgN)) return 0;
+  const int t = effective_tune(prec, lgN, kind, tune);
+  if (prec == 2) return t ? pass_tile_c128_2(lgN, strided, kind) : pass_tile_c128_0(lgN, strided, kind);
+  if (prec == 3) return pass_tile_c64x_0(lgN, strided, kind);
+  switch (t) {
+    case 1: return pass_tile_c64_1(lgN, strided, kind);
+    case 2: return pass_tile_c64_2(lgN, strided, kind);
+    case 3: return pass_tile_c64_3(lgN, strided, kind);
+    default: return pass_tile_c64_0(lgN, strided, kind);
+  }
 }
 
 // ---------------------------------------------------------------------------

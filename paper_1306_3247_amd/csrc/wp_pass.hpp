@@ -30,14 +30,24 @@ constexpr int pow2_floor(int x) {
 constexpr int imin(int a, int b) { return a < b ? a : b; }
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 
-template <class S, class R, int N, bool STRIDED, int KIND>
+// Tuning variants (picked per precision, line length, layout and kind by
+// the autotuner of the C ABI): bit 0 gives FP32 passes 8 values per thread
+// instead of 16; bit 1 aims at 256 threads and 52 KiB of LDS per workgroup
+// (three per CU) instead of 512 threads and 80 KiB (two per CU).  Variants
+// other than 0 are compiled for line lengths 64..1024 and kinds F, V, K.
+constexpr int kTuneVariants = 4;
+constexpr bool tune_compiled(int N, int KIND) { return N >= 64 && N <= 1024 && KIND <= 2; }
+
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE = 0>
 struct pass_cfg {
   static constexpr int ELEM = (int)sizeof(cx<R>);   // LDS element (compute type)
   static constexpr int GELEM = (int)sizeof(cx<S>);  // HBM element (storage type)
   // 16 values per thread in FP32 (8 in FP64) halves the threads per line;
   // the split 1D potential pass, with a twiddle and an FP64 phase per value,
   // keeps 8 to stay within its registers.
-  static constexpr int VPT = (ELEM == 8 && N >= 16 && KIND != PK_VS) ? 16 : (N < 8 ? N : 8);
+  static constexpr int VPT0 = (ELEM == 8 && N >= 16 && KIND != PK_VS) ? 16 : (N < 8 ? N : 8);
+  static constexpr int VPT = ((TUNE & 1) && VPT0 == 16) ? 8 : VPT0;
+  static constexpr int TGT = (TUNE & 2) ? 256 : 512;  // threads aimed at
   static constexpr int L = N / VPT;
   static constexpr bool EXCH = N > 8;  // more than one stage: exchanges through LDS
   // Padded line length (see pad16).
@@ -45,14 +55,14 @@ struct pass_cfg {
   static constexpr bool TW_LDS = N <= 512;
   static constexpr int TW_BYTES = 16 * tw_count(N);
   static constexpr int TAB_BYTES = KIND == PK_K ? 16 * N : 0;  // kinetic factors
-  // At most 80 KiB of LDS per workgroup (two per CU).
-  static constexpr int BUDGET = 81920 - 1024;
+  // At most 80 KiB of LDS per workgroup (two per CU), 52 KiB in variant 2.
+  static constexpr int BUDGET = ((TUNE & 2) ? 53248 : 81920) - 1024;
   static constexpr int DATA_BUDGET = BUDGET - (TW_LDS ? TW_BYTES : 0) - TAB_BYTES;
   static constexpr int T_LDS = EXCH ? imax(1, pow2_floor(DATA_BUDGET / (NP * ELEM))) : 4096;
-  static constexpr int T_THR = imax(1, 512 / L);
+  static constexpr int T_THR = imax(1, TGT / L);
   // Strided lines: enough neighbouring lines that each row segment read is
-  // a whole 128-byte cache line, within 512 threads.
-  static constexpr int T_MIN = STRIDED ? imin(128 / GELEM, imax(1, 512 / L)) : 1;
+  // a whole 128-byte cache line, within the thread target.
+  static constexpr int T_MIN = STRIDED ? imin(128 / GELEM, imax(1, TGT / L)) : 1;
   static constexpr int TILE = imin(T_LDS, imax(T_THR, T_MIN));
   static constexpr int THREADS = TILE * L;
   // Row segments shorter than a cache line: the two workgroups that share
@@ -63,8 +73,9 @@ struct pass_cfg {
   // the line data is in registers.
   static constexpr int DATA_BYTES = imax(EXCH ? TILE * NP * ELEM : 0, KIND == PK_V ? 16 * N : 0);
   // Waves per SIMD the register allocation must leave room for: two
-  // workgroups per CU (at most 128 VGPRs for 512-thread workgroups).
-  static constexpr int WAVES_EU = imax(1, imin(4, THREADS / 128));
+  // workgroups per CU (at most 128 VGPRs for 512-thread workgroups); three
+  // 256-thread workgroups in variant 2.
+  static constexpr int WAVES_EU = (TUNE & 2) ? imax(1, imin(4, 3 * THREADS / 256)) : imax(1, imin(4, THREADS / 128));
 };
 
 __device__ __forceinline__ void decode_line(const GridDev &g, int axis, int64_t o, int64_t c, int idx[3]) {
@@ -107,9 +118,9 @@ __device__ __forceinline__ cx<double> split_twiddle(const PassArgs &a, int64_t e
 
 // The work of one workgroup: tile `blk` of the lines described by `a`;
 // `coef` holds the CO_COUNT waveform values at the pass's time (kind V).
-template <class S, class R, int N, bool STRIDED, int KIND>
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
 __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef, unsigned blk) {
-  using C = pass_cfg<S, R, N, STRIDED, KIND>;
+  using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
   using T = typename storage<S>::type;
   constexpr int L = C::L, VPT = C::VPT, TILE = C::TILE, NT = C::THREADS;
 
@@ -277,141 +288,130 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
   }
 }
 
-template <class S, class R, int N, bool STRIDED, int KIND>
-__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
-                                  (pass_cfg<S, R, N, STRIDED, KIND>::WAVES_EU))
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
+__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND, TUNE>::THREADS),
+                                  (pass_cfg<S, R, N, STRIDED, KIND, TUNE>::WAVES_EU))
     pass_kernel(PassArgs a) {
-  using C = pass_cfg<S, R, N, STRIDED, KIND>;
+  using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
   const unsigned blk = C::PAIR ? pair_blocks(blockIdx.x, gridDim.x) : blockIdx.x;
-  pass_body<S, R, N, STRIDED, KIND>(a, a.coef, blk);
+  pass_body<S, R, N, STRIDED, KIND, TUNE>(a, a.coef, blk);
 }
 
 // Batched: workgroup b runs tile items[b].tile of solve items[b].solve, whose
 // argument block is args[items[b].solve * nvar + var]; `row` selects the
 // waveform values of the step this launch belongs to.
-template <class S, class R, int N, bool STRIDED, int KIND>
-__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND>::THREADS),
-                                  (pass_cfg<S, R, N, STRIDED, KIND>::WAVES_EU))
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
+__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND, TUNE>::THREADS),
+                                  (pass_cfg<S, R, N, STRIDED, KIND, TUNE>::WAVES_EU))
     batch_pass_kernel(const PassArgs *args, const BatchItem *items, int nvar, int var, int row) {
   const BatchItem it = items[blockIdx.x];
   // A reference into global memory, not a copy: the fields are read with
   // scalar loads (the address is uniform), no private copy of the block.
   const PassArgs &a = args[it.solve * nvar + var];
-  pass_body<S, R, N, STRIDED, KIND>(a, a.coef ? a.coef + row * CO_COUNT : nullptr, (unsigned)it.tile);
+  pass_body<S, R, N, STRIDED, KIND, TUNE>(a, a.coef ? a.coef + row * CO_COUNT : nullptr, (unsigned)it.tile);
 }
 
-template <class S, class R, int N, bool STRIDED, int KIND>
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
 hipError_t launch_batch_t(const BatchLaunch &b, hipStream_t s) {
-  using C = pass_cfg<S, R, N, STRIDED, KIND>;
-  hipLaunchKernelGGL((batch_pass_kernel<S, R, N, STRIDED, KIND>), dim3(b.nblocks), dim3(C::THREADS), 0, s,
+  using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
+  hipLaunchKernelGGL((batch_pass_kernel<S, R, N, STRIDED, KIND, TUNE>), dim3(b.nblocks), dim3(C::THREADS), 0, s,
                      b.args, b.items, b.nvar, b.var, b.row);
   return hipGetLastError();
 }
 
-template <class S, class R, int N>
-hipError_t launch_batch_n(const BatchLaunch &b, hipStream_t s) {
-  if constexpr (N >= 128 && N <= 1024) {
-    if (b.kind == PK_VS) return launch_batch_t<S, R, N, true, PK_VS>(b, s);
-    if (b.kind == PK_KS) return launch_batch_t<S, R, N, false, PK_KS>(b, s);
-  } else {
-    if (b.kind == PK_VS || b.kind == PK_KS) return hipErrorInvalidValue;
-  }
-  if (b.kind == PK_V) return b.strided ? launch_batch_t<S, R, N, true, PK_V>(b, s) : launch_batch_t<S, R, N, false, PK_V>(b, s);
-  if (b.kind == PK_K) return b.strided ? launch_batch_t<S, R, N, true, PK_K>(b, s) : launch_batch_t<S, R, N, false, PK_K>(b, s);
-  return b.strided ? launch_batch_t<S, R, N, true, PK_F>(b, s) : launch_batch_t<S, R, N, false, PK_F>(b, s);
-}
-
-template <class S, class R>
-hipError_t dispatch_batch(const BatchLaunch &b, hipStream_t s) {
-  switch (b.lgN) {
-    case 1: return launch_batch_n<S, R, 2>(b, s);
-    case 2: return launch_batch_n<S, R, 4>(b, s);
-    case 3: return launch_batch_n<S, R, 8>(b, s);
-    case 4: return launch_batch_n<S, R, 16>(b, s);
-    case 5: return launch_batch_n<S, R, 32>(b, s);
-    case 6: return launch_batch_n<S, R, 64>(b, s);
-    case 7: return launch_batch_n<S, R, 128>(b, s);
-    case 8: return launch_batch_n<S, R, 256>(b, s);
-    case 9: return launch_batch_n<S, R, 512>(b, s);
-    case 10: return launch_batch_n<S, R, 1024>(b, s);
-    case 11: return launch_batch_n<S, R, 2048>(b, s);
-    case 12: return launch_batch_n<S, R, 4096>(b, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-// Lines per workgroup of a pass configuration (the host sizes block maps with it).
-template <class S, class R>
-int pass_tile_t(int lgN, bool strided, int kind) {
-  auto pick = [&](auto n) -> int {
-    constexpr int NN = decltype(n)::value;
-    if constexpr (NN >= 128 && NN <= 1024) {
-      if (kind == PK_VS) return pass_cfg<S, R, NN, true, PK_VS>::TILE;
-      if (kind == PK_KS) return pass_cfg<S, R, NN, false, PK_KS>::TILE;
-    } else {
-      if (kind == PK_VS || kind == PK_KS) return 0;
-    }
-    if (kind == PK_V) return strided ? pass_cfg<S, R, NN, true, PK_V>::TILE : pass_cfg<S, R, NN, false, PK_V>::TILE;
-    if (kind == PK_K) return strided ? pass_cfg<S, R, NN, true, PK_K>::TILE : pass_cfg<S, R, NN, false, PK_K>::TILE;
-    return strided ? pass_cfg<S, R, NN, true, PK_F>::TILE : pass_cfg<S, R, NN, false, PK_F>::TILE;
-  };
-  switch (lgN) {
-    case 1: return pick(std::integral_constant<int, 2>{});
-    case 2: return pick(std::integral_constant<int, 4>{});
-    case 3: return pick(std::integral_constant<int, 8>{});
-    case 4: return pick(std::integral_constant<int, 16>{});
-    case 5: return pick(std::integral_constant<int, 32>{});
-    case 6: return pick(std::integral_constant<int, 64>{});
-    case 7: return pick(std::integral_constant<int, 128>{});
-    case 8: return pick(std::integral_constant<int, 256>{});
-    case 9: return pick(std::integral_constant<int, 512>{});
-    case 10: return pick(std::integral_constant<int, 1024>{});
-    case 11: return pick(std::integral_constant<int, 2048>{});
-    case 12: return pick(std::integral_constant<int, 4096>{});
-    default: return 0;
-  }
-}
-
-template <class S, class R, int N, bool STRIDED, int KIND>
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
 hipError_t launch_pass_t(const PassArgs &a, hipStream_t s) {
-  using C = pass_cfg<S, R, N, STRIDED, KIND>;
+  using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
   const int64_t blocks = (a.n_lines + C::TILE - 1) / C::TILE;
-  hipLaunchKernelGGL((pass_kernel<S, R, N, STRIDED, KIND>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+  hipLaunchKernelGGL((pass_kernel<S, R, N, STRIDED, KIND, TUNE>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
-template <class S, class R, int N>
-hipError_t launch_pass_n(const PassArgs &a, hipStream_t s) {
-  const bool strided = a.lg_inner > 0;
-  if (a.ops & OP_SPLIT) {
-    if constexpr (N >= 128 && N <= 1024) {
-      if (a.axis == 0 && strided) return launch_pass_t<S, R, N, true, PK_VS>(a, s);
-      if (a.axis == 1 && !strided) return launch_pass_t<S, R, N, false, PK_KS>(a, s);
+// What one launch needs: kind (PK_*), layout, tuning variant.  The kind of a
+// single pass follows from its operations.
+__host__ inline int pass_kind_of(const PassArgs &a) {
+  if (a.ops & OP_SPLIT) return a.axis == 0 ? PK_VS : PK_KS;
+  if (a.ops & OP_V) return PK_V;
+  if (a.ops & OP_K) return PK_K;
+  return PK_F;
+}
+
+// Call f(integral_constant<N>) for N = 2^lgN, 1 <= lgN <= 12.
+template <class F>
+__host__ inline auto with_n(int lgN, F &&f) -> decltype(f(std::integral_constant<int, 2>{})) {
+  switch (lgN) {
+    case 1: return f(std::integral_constant<int, 2>{});
+    case 2: return f(std::integral_constant<int, 4>{});
+    case 3: return f(std::integral_constant<int, 8>{});
+    case 4: return f(std::integral_constant<int, 16>{});
+    case 5: return f(std::integral_constant<int, 32>{});
+    case 6: return f(std::integral_constant<int, 64>{});
+    case 7: return f(std::integral_constant<int, 128>{});
+    case 8: return f(std::integral_constant<int, 256>{});
+    case 9: return f(std::integral_constant<int, 512>{});
+    case 10: return f(std::integral_constant<int, 1024>{});
+    case 11: return f(std::integral_constant<int, 2048>{});
+    default: return f(std::integral_constant<int, 4096>{});
+  }
+}
+
+// Call f(KIND, STRIDED) as compile-time constants for the combinations that
+// exist: F, V, K in both layouts; VS strided; KS contiguous.
+template <int N, int TUNE, class F>
+__host__ inline hipError_t with_kind(int kind, bool strided, F &&f) {
+  using std::integral_constant;
+  using T = integral_constant<bool, true>;
+  using U = integral_constant<bool, false>;
+  if constexpr (TUNE != 0 && !tune_compiled(N, 0)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (kind == PK_V) return strided ? f(integral_constant<int, PK_V>{}, T{}) : f(integral_constant<int, PK_V>{}, U{});
+    if (kind == PK_K) return strided ? f(integral_constant<int, PK_K>{}, T{}) : f(integral_constant<int, PK_K>{}, U{});
+    if (kind == PK_F) return strided ? f(integral_constant<int, PK_F>{}, T{}) : f(integral_constant<int, PK_F>{}, U{});
+    if constexpr (TUNE == 0 && N >= 128 && N <= 1024) {
+      if (kind == PK_VS && strided) return f(integral_constant<int, PK_VS>{}, T{});
+      if (kind == PK_KS && !strided) return f(integral_constant<int, PK_KS>{}, U{});
     }
     return hipErrorInvalidValue;
   }
-  if (a.ops & OP_V) return strided ? launch_pass_t<S, R, N, true, PK_V>(a, s) : launch_pass_t<S, R, N, false, PK_V>(a, s);
-  if (a.ops & OP_K) return strided ? launch_pass_t<S, R, N, true, PK_K>(a, s) : launch_pass_t<S, R, N, false, PK_K>(a, s);
-  return strided ? launch_pass_t<S, R, N, true, PK_F>(a, s) : launch_pass_t<S, R, N, false, PK_F>(a, s);
 }
 
-template <class S, class R>
+// The entry points each precision-and-variant translation unit instantiates.
+template <class S, class R, int TUNE>
 hipError_t dispatch_pass(int lgN, const PassArgs &a, hipStream_t s) {
-  switch (lgN) {
-    case 1: return launch_pass_n<S, R, 2>(a, s);
-    case 2: return launch_pass_n<S, R, 4>(a, s);
-    case 3: return launch_pass_n<S, R, 8>(a, s);
-    case 4: return launch_pass_n<S, R, 16>(a, s);
-    case 5: return launch_pass_n<S, R, 32>(a, s);
-    case 6: return launch_pass_n<S, R, 64>(a, s);
-    case 7: return launch_pass_n<S, R, 128>(a, s);
-    case 8: return launch_pass_n<S, R, 256>(a, s);
-    case 9: return launch_pass_n<S, R, 512>(a, s);
-    case 10: return launch_pass_n<S, R, 1024>(a, s);
-    case 11: return launch_pass_n<S, R, 2048>(a, s);
-    case 12: return launch_pass_n<S, R, 4096>(a, s);
-    default: return hipErrorInvalidValue;
-  }
+  const int kind = pass_kind_of(a);
+  const bool strided = a.lg_inner > 0;
+  return with_n(lgN, [&](auto n) -> hipError_t {
+    constexpr int NN = decltype(n)::value;
+    return with_kind<NN, TUNE>(kind, strided, [&](auto k, auto st) -> hipError_t {
+      return launch_pass_t<S, R, NN, decltype(st)::value, decltype(k)::value, TUNE>(a, s);
+    });
+  });
+}
+
+template <class S, class R, int TUNE>
+hipError_t dispatch_batch(const BatchLaunch &b, hipStream_t s) {
+  return with_n(b.lgN, [&](auto n) -> hipError_t {
+    constexpr int NN = decltype(n)::value;
+    return with_kind<NN, TUNE>(b.kind, b.strided, [&](auto k, auto st) -> hipError_t {
+      return launch_batch_t<S, R, NN, decltype(st)::value, decltype(k)::value, TUNE>(b, s);
+    });
+  });
+}
+
+// Lines per workgroup of a pass configuration (the host sizes block maps
+// with it); 0 for a combination that is not compiled.
+template <class S, class R, int TUNE>
+int pass_tile_t(int lgN, bool strided, int kind) {
+  int tile = 0;
+  (void)with_n(lgN, [&](auto n) -> hipError_t {
+    constexpr int NN = decltype(n)::value;
+    return with_kind<NN, TUNE>(kind, strided, [&](auto k, auto st) -> hipError_t {
+      tile = pass_cfg<S, R, NN, decltype(st)::value, decltype(k)::value, TUNE>::TILE;
+      return hipSuccess;
+    });
+  });
+  return tile;
 }
 
 }  // namespace wp

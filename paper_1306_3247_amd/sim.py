@@ -90,6 +90,11 @@ def _load() -> C.CDLL:
         "wp_synchronize": [vp],
         "wp_profile_propagate": [vp, u64, P(d), P(u64)],
         "wp_store_reference": [vp],
+        "wp_time_pass": [vp, C.c_int32, C.c_uint32, P(d)],
+        "wp_autotune": [vp, C.c_uint32, P(d)],
+        "wp_batch_autotune": [vp, C.c_uint32],
+        "wp_tune_get": [C.c_int32] * 5 + [P(C.c_int32)],
+        "wp_tune_set": [C.c_int32] * 6,
         "wp_inner": [vp, vp, C.c_int32, P(d)],
         "wp_batch_create": [P(vp), C.c_uint32, vp, P(vp)],
         "wp_batch_set_graph_steps": [vp, C.c_uint32],
@@ -107,6 +112,8 @@ def _load() -> C.CDLL:
     L.wp_version.restype = C.c_char_p
     L.wp_batch_last_error.argtypes = [vp]
     L.wp_batch_last_error.restype = C.c_char_p
+    L.wp_tune_clear.argtypes = []
+    L.wp_tune_clear.restype = None
     return L
 
 
@@ -163,6 +170,31 @@ def workspace_bytes(grid, precision: str) -> int:
     if rc:
         raise WavepacketError(rc, "wp_workspace_bytes")
     return out.value
+
+
+PASS_KIND_IDS = {"fft": 0, "potential": 1, "kinetic": 2, "split_potential": 3, "split_kinetic": 4}
+TUNE_VARIANTS = 4
+
+
+def tune_get(batched: bool, precision: str, lg_n: int, strided: bool, kind: str) -> int:
+    """Variant in the process-wide tuning table for one pass shape."""
+    out = C.c_int32()
+    rc = lib.wp_tune_get(int(batched), PRECISIONS[precision], int(lg_n), int(strided), PASS_KIND_IDS[kind],
+                         C.byref(out))
+    if rc:
+        raise WavepacketError(rc, "wp_tune_get")
+    return out.value
+
+
+def tune_set(batched: bool, precision: str, lg_n: int, strided: bool, kind: str, variant: int) -> None:
+    rc = lib.wp_tune_set(int(batched), PRECISIONS[precision], int(lg_n), int(strided), PASS_KIND_IDS[kind],
+                         int(variant))
+    if rc:
+        raise WavepacketError(rc, "wp_tune_set")
+
+
+def tune_clear() -> None:
+    lib.wp_tune_clear()
 
 
 def _arr3(v, fill: float):
@@ -290,6 +322,29 @@ class Simulation:
         self._check(lib.wp_profile_propagate(self._h, int(nsteps), ms, cnt), "wp_profile_propagate")
         return {k: (cnt[i], ms[i]) for i, k in enumerate(self.PASS_KINDS) if cnt[i]}
 
+    def time_pass(self, kind: str, reps: int = 20) -> float:
+        """Average device milliseconds of one line pass of class `kind`
+        (see PASS_KINDS) over `reps` back-to-back launches.  Measurement
+        only: the state is not a solution afterwards."""
+        ms = C.c_double()
+        self._check(lib.wp_time_pass(self._h, self.PASS_KINDS.index(kind), int(reps), C.byref(ms)), "wp_time_pass")
+        return ms.value
+
+    TUNE_CLASSES = ("axis0", "mid", "last")
+
+    def autotune(self, reps: int = 10) -> dict:
+        """Time every kernel variant of this grid's line passes and store the
+        fastest in the tuning table; returns {class: {variant: ms}}."""
+        ms = (C.c_double * (3 * TUNE_VARIANTS))()
+        self._check(lib.wp_autotune(self._h, int(reps), ms), "wp_autotune")
+        out = {}
+        for c, name in enumerate(self.TUNE_CLASSES):
+            row = {v: ms[c * TUNE_VARIANTS + v] for v in range(TUNE_VARIANTS)
+                   if ms[c * TUNE_VARIANTS + v] == ms[c * TUNE_VARIANTS + v]}
+            if row:
+                out[name] = row
+        return out
+
     def state_ptr(self) -> int:
         return lib.wp_state_ptr(self._h)
 
@@ -328,6 +383,11 @@ class Batch:
 
     def propagate(self, nsteps: int) -> None:
         self._check(lib.wp_batch_propagate(self._h, int(nsteps)), "wp_batch_propagate")
+
+    def autotune(self, reps: int = 10) -> None:
+        """Pick the fastest kernel variant of each pass group (members'
+        states are saved and restored)."""
+        self._check(lib.wp_batch_autotune(self._h, int(reps)), "wp_batch_autotune")
 
     def close(self) -> None:
         if getattr(self, "_h", None):
