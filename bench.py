@@ -31,7 +31,8 @@ METRIC = "site-steps/s at 3D 512³ FP32 vs FP64; p50/p99 latency of served solve
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("paper_1306_3247_amd/csrc/wp_kernels.hip", "paper_1306_3247_amd/csrc/wp_device.hpp",
                   "paper_1306_3247_amd/csrc/wp_internal.hpp", "paper_1306_3247_amd/csrc/wp_pass.hpp",
-                  "paper_1306_3247_amd/csrc/wp_pass_c64.hip")
+                  "paper_1306_3247_amd/csrc/wp_pass_c64.hip", "paper_1306_3247_amd/csrc/wp_pass_c64_t1.hip",
+                  "paper_1306_3247_amd/csrc/wp_pass_c64_t2.hip", "paper_1306_3247_amd/csrc/wp_pass_c64_t3.hip")
 
 
 def kernel_hash() -> str:
@@ -42,7 +43,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kind: str, workload: str):
+def traffic_for(kind: str, workload: str, tune: int = 0):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel sources; else None."""
     try:
@@ -52,7 +53,7 @@ def traffic_for(kind: str, workload: str):
         return None
     if t.get("kernel_hash") != kernel_hash():
         return None
-    e = t.get("entries", {}).get(f"{workload}:{kind}")
+    e = t.get("entries", {}).get(f"{workload}:{kind}:t{tune}")
     return None if e is None else e.get("bytes_per_launch")
 
 
@@ -320,11 +321,17 @@ def main() -> int:
     state_bytes = S.state_bytes(prob.grid, "c64")
     alg_bytes = 2 * state_bytes
     timed = {k: s32.time_pass(k, args.pass_reps) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
+    lg = int(np.log2(args.n))
+    variant = {"axis0": S.tune_get(False, "c64", lg, True, "potential"),
+               "mid_fwd": S.tune_get(False, "c64", lg, True, "fft"),
+               "mid_inv": S.tune_get(False, "c64", lg, True, "fft"),
+               "last": S.tune_get(False, "c64", lg, False, "kinetic")}
     kind, avg_ms = max(timed.items(), key=lambda kv: kv[1])
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": f"pass:{kind}", "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": traffic_for(kind, workload), "avg_launch_ms": round(avg_ms, 4),
+                       "traffic": traffic_for(kind, workload, variant[kind]), "variant": variant[kind],
+                       "avg_launch_ms": round(avg_ms, 4),
                        "alg_bytes_per_launch": alg_bytes, "reps": args.pass_reps,
                        "passes": {k: {"avg_ms": round(m, 4),
                                       "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)} for k, m in timed.items()},
