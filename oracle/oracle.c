@@ -35,11 +35,14 @@ int orc_num_threads(void) {
 
 static int is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
 
+/* Any axis length n >= 2 is accepted: the transform below handles every
+ * factorisation (the paper advises lengths with small prime factors for
+ * speed, Section 3.3, not for correctness). */
 static int grid_ok(const orc_grid *g) {
   if (g->ndim < 1 || g->ndim > 3) return 0;
   for (int d = 0; d < 3; ++d) {
     if (d < g->ndim) {
-      if (g->n[d] < 2 || !is_pow2(g->n[d])) return 0;
+      if (g->n[d] < 2) return 0;
       if (!(g->hi[d] > g->lo[d])) return 0;
     } else if (g->n[d] != 1) {
       return 0;
@@ -95,15 +98,15 @@ int orc_coords(const orc_grid *g, int axis, double *out) {
 
 /* Momentum grid p_i = 2 pi hbar i / (n dx) (Section 2.1, after eq. ft); the
  * wavenumber k = p / hbar is stored in DFT output order: index m < n/2 holds
- * m, index m >= n/2 holds m - n (the Nyquist bin m = n/2 becomes -n/2; the
- * paper's list i = -n/2..n/2 has one entry too many, and k^2 is the same for
- * either sign). */
+ * m, index m >= n/2 holds m - n (the Nyquist bin m = n/2 of an even n becomes
+ * -n/2; the paper's list i = -n/2..n/2 has one entry too many, and k^2 is the
+ * same for either sign; for odd n the bins are -(n-1)/2..(n-1)/2). */
 int orc_wavenumbers(const orc_grid *g, int axis, double *out) {
   if (!grid_ok(g) || axis < 0 || axis > 2) return ORC_EINVAL;
   int64_t n = g->n[axis];
   double L = (double)n * spacing(g, axis);
   for (int64_t m = 0; m < n; ++m) {
-    int64_t mm = (m < n / 2) ? m : m - n;
+    int64_t mm = (2 * m < n) ? m : m - n;
     out[m] = 2.0 * ORC_PI * (double)mm / L;
   }
   if (n == 1) out[0] = 0.0;
@@ -201,6 +204,62 @@ static void fft_line(int64_t n, double complex *a, const double complex *tw, int
   }
 }
 
+/* exp(dir 2 pi i e / n), the exponent reduced exactly mod n first. */
+static double complex unit_root(int64_t e, int64_t n, int dir) {
+  double ang = 2.0 * ORC_PI * (double)(e % n) / (double)n;
+  return cos(ang) + dir * I * sin(ang);
+}
+
+static int64_t smallest_factor(int64_t n) {
+  for (int64_t p = 2; p * p <= n; ++p)
+    if (n % p == 0) return p;
+  return n;
+}
+
+/* Mixed-radix decimation in time (Cooley and Tukey) for any n: with p the
+ * smallest prime factor of n and m = n/p, the m-point transforms Y_r of the
+ * subsequences x[r + p j] (r < p) give X[k + m q] = sum_r W^(r (k + m q)) Y_r[k],
+ * W = exp(dir 2 pi i / n).  Reads in[j*stride], writes out[0..n); tmp holds n
+ * values.  Unnormalised. */
+static void fft_mixed(int64_t n, const double complex *in, int64_t stride, double complex *out,
+                      double complex *tmp, int dir) {
+  if (n == 1) {
+    out[0] = in[0];
+    return;
+  }
+  int64_t p = smallest_factor(n), m = n / p;
+  for (int64_t r = 0; r < p; ++r) fft_mixed(m, in + r * stride, stride * p, tmp + r * m, out + r * m, dir);
+  for (int64_t k = 0; k < m; ++k)
+    for (int64_t q = 0; q < p; ++q) {
+      double complex acc = 0.0;
+      for (int64_t r = 0; r < p; ++r) acc += unit_root(r * (k + m * q), n, dir) * tmp[r * m + k];
+      out[k + m * q] = acc;
+    }
+}
+
+/* One line of any length: radix 2 for powers of two, the mixed-radix
+ * recursion otherwise; the inverse (dir = +1) divides by n. */
+static int line_transform(int64_t n, double complex *a, const double complex *tw, int dir) {
+  if (is_pow2(n)) {
+    fft_line(n, a, tw, dir);
+    return ORC_OK;
+  }
+  double complex *src = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+  double complex *tmp = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+  if (!src || !tmp) {
+    free(src);
+    free(tmp);
+    return ORC_ENOMEM;
+  }
+  memcpy(src, a, sizeof(double complex) * (size_t)n);
+  fft_mixed(n, src, 1, a, tmp, dir);
+  if (dir == 1)
+    for (int64_t i = 0; i < n; ++i) a[i] /= (double)n;
+  free(src);
+  free(tmp);
+  return ORC_OK;
+}
+
 static double complex *twiddles(int64_t n, int dir) {
   double complex *tw = (double complex *)malloc(sizeof(double complex) * (size_t)(n / 2 + 1));
   if (!tw) return NULL;
@@ -212,13 +271,13 @@ static double complex *twiddles(int64_t n, int dir) {
 }
 
 int orc_fft1d(int64_t n, double complex *data, int dir) {
-  if (!is_pow2(n) || (dir != -1 && dir != 1)) return ORC_EINVAL;
+  if (n < 1 || (dir != -1 && dir != 1)) return ORC_EINVAL;
   if (n == 1) return ORC_OK;
   double complex *tw = twiddles(n, dir);
   if (!tw) return ORC_ENOMEM;
-  fft_line(n, data, tw, dir);
+  int rc = line_transform(n, data, tw, dir);
   free(tw);
-  return ORC_OK;
+  return rc;
 }
 
 /* 1D transform along one axis of the row-major array: each line is copied
@@ -246,7 +305,10 @@ static int fft_axis(const orc_grid *g, double complex *psi, int axis, int dir) {
       int64_t o = l / inner, c = l % inner;
       double complex *base = psi + o * n * inner + c;
       for (int64_t i = 0; i < n; ++i) buf[i] = base[i * inner];
-      fft_line(n, buf, tw, dir);
+      if (line_transform(n, buf, tw, dir) != ORC_OK) {
+#pragma omp atomic write
+        fail = 1;
+      }
       for (int64_t i = 0; i < n; ++i) base[i * inner] = buf[i];
     }
     free(buf);

@@ -58,9 +58,22 @@ def test_impulse_and_constant(oracle_mod):
         assert np.abs(F - e).max() <= 1e-12
 
 
-def test_fft_rejects_non_power_of_two(oracle_mod):
+@pytest.mark.parametrize("n", [3, 5, 6, 7, 9, 10, 12, 14, 15, 21, 25, 30, 35, 49, 60, 63, 11, 13, 22, 105, 120])
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_mixed_radix_fft_matches_bruteforce_dft_and_numpy(oracle_mod, n, direction):
+    """Lengths with factors 3, 5, 7 (the sizes the paper advises besides
+    powers of two) and other primes, against the O(n^2) definition and
+    numpy's FFT."""
+    x = W.random_state((n,), seed=100 + n)
+    got = oracle_mod.fft(x, direction)
+    assert rel_l2(got, oracle_mod.dft(x, direction)) <= 1e-13
+    ref = np.fft.fft(x) if direction == -1 else np.fft.ifft(x)
+    assert rel_l2(got, ref) <= 1e-13
+
+
+def test_fft_rejects_empty(oracle_mod):
     with pytest.raises(RuntimeError):
-        oracle_mod.fft(np.ones(6), -1)
+        oracle_mod.fft(np.ones(0), -1)
 
 
 # --- grid and momentum grid (Section 2.1, eqs. grid, Deltax) -----------------
@@ -73,17 +86,17 @@ def test_grid_points_half_open(oracle_mod):
     assert np.allclose(np.diff(x), 0.5, rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("n", [8, 9 - 1, 16])
+@pytest.mark.parametrize("n", [8, 16, 9, 15, 12, 21])
 def test_plane_waves_are_kinetic_eigenstates(oracle_mod, n):
-    """exp(i k x) on the periodic grid, k = 2 pi m/L for m = -n/2..n/2-1, is an
-    exact eigenstate of the free step with phase exp(-i hbar k^2 dt/2m).  This
-    pins the wavenumber of every DFT bin, negative and Nyquist included, the
-    kinetic sign, hbar and the mass."""
+    """exp(i k x) on the periodic grid, k = 2 pi m/L for m = -n/2..n/2-1 (even
+    n) or -(n-1)/2..(n-1)/2 (odd n), is an exact eigenstate of the free step
+    with phase exp(-i hbar k^2 dt/2m).  This pins the wavenumber of every DFT
+    bin, negative and Nyquist included, the kinetic sign, hbar and the mass."""
     L = 5.0
     g = W.Grid(1, [n], [-1.0], [-1.0 + L], mass=1.7, hbar=0.9, dt=0.3)
     x = -1.0 + np.arange(n) * (L / n)
     pot = W.Potential()
-    for m in range(-n // 2, n // 2):
+    for m in (range(-n // 2, n // 2) if n % 2 == 0 else range(-(n // 2), n // 2 + 1)):
         k = 2 * np.pi * m / L
         psi = np.exp(1j * k * x)
         out = oracle_mod.propagate(g, pot, psi, 1)
@@ -105,13 +118,15 @@ def free_gaussian(x, c, sigma, k, t, hbar=1.0, mass=1.0):
     return A * np.sqrt(a0 / a) * np.exp(b * b / (4 * a) - k * k * sigma * sigma / 4)
 
 
-def test_free_gaussian_1d_closed_form(oracle_mod):
-    g = W.Grid(1, [512], [-40.0], [40.0], mass=1.0, hbar=1.0, dt=0.02)
+@pytest.mark.parametrize("n", [512, 420, 375])
+def test_free_gaussian_1d_closed_form(oracle_mod, n):
+    """Powers of two and mixed lengths (420 = 2^2 3 5 7, 375 = 3 5^3)."""
+    g = W.Grid(1, [n], [-40.0], [40.0], mass=1.0, hbar=1.0, dt=0.02)
     c, s, k = -5.0, 1.0, 2.0
     psi0 = oracle_mod.gaussian(g, [c], [s], [k])
     x = oracle_mod.coords(g, 0)
     # The discrete renormalisation differs from 1 only by round-off here.
-    assert abs(np.sum(abs(free_gaussian(x, c, s, k, 0.0)) ** 2) * 80 / 512 - 1) < 1e-14
+    assert abs(np.sum(abs(free_gaussian(x, c, s, k, 0.0)) ** 2) * 80 / n - 1) < 1e-14
     out = oracle_mod.propagate(g, W.Potential(), psi0, 100)  # t = 2
     assert rel_l2(out, free_gaussian(x, c, s, k, 2.0)) <= 1e-12
 
