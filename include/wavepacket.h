@@ -19,8 +19,10 @@
  * the device; the result equals the unmerged product up to rounding.
  *
  * Conventions shared by every entry point
- *   - Grid: axis d has n[d] points, a power of two >= 2, on the half-open
- *     interval [lo[d], hi[d]) with spacing (hi-lo)/n and x_i = lo + i*spacing.
+ *   - Grid: axis d has n[d] >= 2 points (see wp_create for the supported
+ *     lengths) on the half-open interval [lo[d], hi[d]) with spacing
+ *     (hi-lo)/n and x_i = lo + i*spacing.  DFT bin m holds the wavenumber
+ *     2 pi m'/(hi-lo) with m' = m for 2m < n and m - n otherwise.
  *     1D problems lie along x and 2D problems in the xy-plane (Section 2.2);
  *     unused axes have n = 1.  Boundaries are periodic.
  *   - State psi: row-major [n0][n1][n2] (last axis contiguous), interleaved
@@ -148,13 +150,18 @@ wp_status wp_workspace_bytes(const wp_grid_desc *grid, uint64_t *bytes);
  * set-up of `initialize_potential`, Section 3.2.2).  `stream` is a
  * hipStream_t or NULL.  The state is zero and the time 0 until a set_state
  * call; the state buffer itself is allocated on first use unless one is
- * bound with wp_bind_state.  Errors: WP_EINVAL (bad descriptor: ndim not in 1..3, n not a power of
- * two or < 2 on a used axis, n != 1 on an unused axis, hi <= lo, mass <= 0,
- * hbar <= 0, dt = 0 or not finite, unknown kinds), WP_EUNSUPPORTED (an axis
- * longer than this build supports: 2^20 points for 1D, where grids above
- * 8192 points are transformed as [n1][n2] with twiddles in between, and
- * 4096 per axis for 2D/3D),
- * WP_ENOMEM, WP_EDEVICE.  On success *out owns all device buffers. */
+ * bound with wp_bind_state.  Axis lengths: powers of two (the fast
+ * kernels), or on grids where some length is not a power of two, lengths
+ * with prime factors 2, 3, 5 and 7 only (the sizes Section 3.3 advises),
+ * transformed by mixed-radix kernels in FP64 arithmetic.  Errors: WP_EINVAL
+ * (bad descriptor: ndim not in 1..3, n < 2 on a used axis, n != 1 on an
+ * unused axis, hi <= lo, mass <= 0, hbar <= 0, dt = 0 or not finite,
+ * unknown kinds), WP_EUNSUPPORTED (a length this build does not transform:
+ * powers of two above 2^20 points in 1D, where grids above 8192 points are
+ * transformed as [n1][n2] with twiddles in between, or above 4096 per axis
+ * in 2D/3D; other lengths with a prime factor above 7 or above 4096
+ * points), WP_ENOMEM, WP_EDEVICE.  On success *out owns all device
+ * buffers. */
 wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void *stream,
                     wp_sim **out);
 
@@ -307,8 +314,9 @@ typedef struct wp_batch wp_batch;
  * member's result equals its own wp_propagate result (same kernels, same
  * reduction order).  The batch's work is ordered on `stream` only: work
  * queued on members' own streams must be complete or on the same stream.
- * Errors: WP_EINVAL (count 0, NULL, a member in K-V-K order), WP_ENOMEM,
- * WP_EDEVICE. */
+ * Errors: WP_EINVAL (count 0, NULL, a member in K-V-K order),
+ * WP_EUNSUPPORTED (a member with a length that is not a power of two),
+ * WP_ENOMEM, WP_EDEVICE. */
 wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_batch **out);
 
 /* Capture runs of k steady steps (1 <= k <= 64) of the 2D/3D members in a

@@ -26,6 +26,10 @@ struct wp_sim {
   // Axes the line passes see: lg, except on a split 1D grid (more than
   // kMaxLine1D points), which is transformed as [n1][n2] = [2^vlg[0]][2^vlg[1]].
   bool split = false;
+  // Some axis length is not a power of two: every pass runs the mixed-radix
+  // kernels with the per-axis stage plans below.
+  bool mixed = false;
+  wp::GPlan plan[3] = {};
   int vdim = 1;
   int vlg[3] = {0, 0, 0};
   int64_t total = 0;
@@ -89,7 +93,7 @@ std::string check_grid(const wp_grid_desc *g) {
   if (g->prec != WP_C64 && g->prec != WP_C128 && g->prec != WP_C64X) return "prec must be WP_C64, WP_C64X or WP_C128";
   for (int d = 0; d < 3; ++d) {
     if (d < g->ndim) {
-      if (g->n[d] < 2 || !is_pow2(g->n[d])) return "n on a used axis must be a power of two >= 2";
+      if (g->n[d] < 2) return "n on a used axis must be >= 2";
       if (!std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]) || !(g->hi[d] > g->lo[d]))
         return "each used axis needs finite lo < hi";
     } else if (g->n[d] != 1) {
@@ -113,7 +117,22 @@ std::string check_pot(const wp_potential_desc *p) {
   return "";
 }
 
+// Prime factors 2, 3, 5, 7 only.
+bool smooth7(uint64_t n) {
+  for (uint64_t p : {2u, 3u, 5u, 7u})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
 std::string check_supported(const wp_grid_desc *g) {
+  bool mixed = false;
+  for (int d = 0; d < g->ndim; ++d) mixed = mixed || !is_pow2(g->n[d]);
+  if (mixed) {
+    for (int d = 0; d < g->ndim; ++d)
+      if (!smooth7(g->n[d]) || g->n[d] > (uint64_t)wp::kMaxMixed)
+        return "axis lengths that are not powers of two must have prime factors 2, 3, 5, 7 only and at most 4096 points";
+    return "";
+  }
   if (g->ndim == 1) {
     if (g->n[0] > (uint64_t)wp::kMaxSplit1D) return "1D grids are limited to 2^20 points in this build";
   } else {
@@ -129,7 +148,7 @@ double spacing(const wp_grid_desc &g, int d) { return (g.hi[d] - g.lo[d]) / (dou
 // m < n/2, m - n otherwise.
 double wavenumber(const wp_grid_desc &g, int d, uint64_t m) {
   const int64_t n = (int64_t)g.n[d];
-  const int64_t mm = ((int64_t)m < n / 2) ? (int64_t)m : (int64_t)m - n;
+  const int64_t mm = (2 * (int64_t)m < n) ? (int64_t)m : (int64_t)m - n;
   return 2.0 * kPi * (double)mm / ((double)n * spacing(g, d));
 }
 
@@ -147,6 +166,38 @@ std::vector<cx<double>> stage_twiddles(uint64_t n) {
           const double ang = 2.0 * kPi * (double)(r * k) / (double)(8 * ls);
           tw.push_back({std::cos(ang), -std::sin(ang)});
         }
+  }
+  if (tw.empty()) tw.push_back({1.0, 0.0});
+  return tw;
+}
+
+// Stage plan and stage-ordered twiddles of a mixed-radix line transform of
+// n points (radix 8 first while 8 divides, then 4 or 2, then 3, 5, 7); stage
+// s with product LS of the earlier radices owns (radix - 1) LS entries
+// exp(-2 pi i r k/(radix LS)) at twoff + (r - 1) LS + k.
+std::vector<cx<double>> mixed_plan(uint64_t n, wp::GPlan *plan) {
+  std::vector<int> rad;
+  uint64_t m = n;
+  while (m % 8 == 0 && m > 1) rad.push_back(8), m /= 8;
+  while (m % 4 == 0) rad.push_back(4), m /= 4;
+  while (m % 2 == 0) rad.push_back(2), m /= 2;
+  for (int p : {3, 5, 7})
+    while (m % p == 0) rad.push_back(p), m /= p;
+  std::vector<cx<double>> tw;
+  *plan = wp::GPlan{};
+  plan->nst = (int32_t)rad.size();
+  uint64_t ls = 1;
+  for (size_t st = 0; st < rad.size(); ++st) {
+    const uint64_t R = (uint64_t)rad[st];
+    plan->radix[st] = (int32_t)R;
+    plan->ls[st] = (int32_t)ls;
+    plan->twoff[st] = (int32_t)tw.size();
+    for (uint64_t r = 1; r < R; ++r)
+      for (uint64_t k = 0; k < ls; ++k) {
+        const double ang = 2.0 * kPi * (double)((r * k) % (R * ls)) / (double)(R * ls);
+        tw.push_back({std::cos(ang), -std::sin(ang)});
+      }
+    ls *= R;
   }
   if (tw.empty()) tw.push_back({1.0, 0.0});
   return tw;
@@ -302,6 +353,19 @@ wp::PassArgs pass_args(const wp_sim *s, int axis, uint32_t ops) {
   return a;
 }
 
+// Launch a line pass of the handle: the power-of-two kernels, or the
+// mixed-radix kernel with the axis's stage plan.
+hipError_t launch_any(const wp_sim *s, const wp::PassArgs &a, hipStream_t st) {
+  if (!s->mixed) return wp::launch_pass(s->prec, a, st);
+  wp::GPassArgs ga{};
+  ga.p = a;
+  ga.inner = 1;
+  for (int d = a.axis + 1; d < 3; ++d) ga.inner *= (int64_t)s->g.n[d];
+  ga.p.n_lines = s->total / (int64_t)s->g.n[a.axis];
+  ga.plan = s->plan[a.axis];
+  return wp::launch_gpass(s->prec == WP_C128 ? 2 : 1, ga, st);
+}
+
 void use_half_kinetic(const wp_sim *s, wp::PassArgs &a) {
   int off = 0;
   for (int d = 0; d < 3; ++d) {
@@ -357,6 +421,11 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
     s->gd.dx[d] = d < grid->ndim ? spacing(*grid, d) : 0.0;
   }
   s->gd.ndim = grid->ndim;
+  for (int d = 0; d < 3; ++d) {
+    s->gd.n[d] = (int32_t)grid->n[d];
+    s->mixed = s->mixed || (d < grid->ndim && !is_pow2(grid->n[d]));
+  }
+  s->gd.pow2 = s->mixed ? 0 : 1;
   s->vdim = grid->ndim;
   for (int d = 0; d < 3; ++d) s->vlg[d] = s->lg[d];
   if (grid->ndim == 1 && grid->n[0] > (uint64_t)wp::kMaxLine1D) {
@@ -396,7 +465,7 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
   if (e == hipSuccess) e = upload(&s->d_k2, k2);
   // Line-FFT twiddles per axis, in the stage order the kernels read them.
   for (int d = 0; d < 3 && e == hipSuccess; ++d)
-    e = upload(&s->d_tw[d], stage_twiddles(uint64_t(1) << s->vlg[d]));
+    e = upload(&s->d_tw[d], s->mixed ? mixed_plan(grid->n[d], &s->plan[d]) : stage_twiddles(uint64_t(1) << s->vlg[d]));
   if (e == hipSuccess && s->split) {
     // exp(-2 pi i e/n), e = q*n1 + r: [n2] factors of q*n1 then [n1] of r.
     const uint64_t n = grid->n[0], n1 = uint64_t(1) << s->vlg[0], n2 = uint64_t(1) << s->vlg[1];
@@ -553,7 +622,7 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
   const int prec = s->prec;
   hipStream_t st = s->stream;
   auto pass = [&](int kind, const wp::PassArgs &a) {
-    return launch(kind, [&]() { return wp::launch_pass(prec, a, st); });
+    return launch(kind, [&]() { return launch_any(s, a, st); });
   };
   // The potential's waveform values come from a table filled for up to
   // kCoefChunk consecutive step times at once; the stream orders each refill
@@ -595,6 +664,8 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
     a.kfull = s->d_kfull;
     a.khalf = s->d_khalf;
     a.tw = s->d_tw[0];
+    if (s->mixed)
+      return launch(WP_PASS_SOLVE1D, [&]() { return wp::launch_gsolve1d(prec == WP_C128 ? 2 : 1, a, s->plan[0], st); });
     return launch(WP_PASS_SOLVE1D, [&]() { return wp::launch_solve1d(prec, a, st); });
   }
   const int last = s->vdim - 1;
@@ -711,9 +782,9 @@ static hipError_t time_launches(wp_sim *s, const wp::PassArgs &a, uint32_t reps,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = wp::launch_pass(s->prec, a, s->stream);
+  if (e == hipSuccess) e = launch_any(s, a, s->stream);
   if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
-  for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = wp::launch_pass(s->prec, a, s->stream);
+  for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_any(s, a, s->stream);
   if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float m = 0.f;
@@ -772,9 +843,9 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
   if (reps < 1 || reps > 10000) return fail(s, WP_EINVAL, "autotune: reps must be in 1..10000");
   if (ms)
     for (int i = 0; i < 3 * wp::kTuneSlots; ++i) ms[i] = NAN;
-  if (s->g.ndim == 1 && !s->split) {
+  if ((s->g.ndim == 1 && !s->split) || s->mixed) {
     s->err.clear();
-    return WP_OK;  // one workgroup solves the whole 1D grid: nothing to tune
+    return WP_OK;  // a 1D grid solved in one workgroup, or mixed lengths: nothing to tune
   }
   (void)hipSetDevice(s->device);
   hipError_t e = ensure_state(s);
@@ -915,11 +986,11 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
     for (int d = 0; d < s->vdim && e == hipSuccess; ++d) {
       wp::PassArgs p = pass_args(s, d, wp::OP_FWD);
       p.psi = s->scratch;
-      if (!wp::pass_supported(s->prec, s->vlg[d])) {
+      if (!s->mixed && !wp::pass_supported(s->prec, s->vlg[d])) {
         e = hipErrorNotSupported;
         break;
       }
-      e = wp::launch_pass(s->prec, p, s->stream);
+      e = launch_any(s, p, s->stream);
     }
     if (e == hipSuccess) {
       wp::ObsArgs k = a;
@@ -1147,6 +1218,8 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
   if (!sims || count == 0) return WP_EINVAL;
   for (uint32_t i = 0; i < count; ++i)
     if (!sims[i] || sims[i]->order != WP_ORDER_VKV) return WP_EINVAL;
+  for (uint32_t i = 0; i < count; ++i)
+    if (sims[i]->mixed) return WP_EUNSUPPORTED;
   wp_batch *b = new (std::nothrow) wp_batch();
   if (!b) return WP_ENOMEM;
   b->sims.assign(sims, sims + count);

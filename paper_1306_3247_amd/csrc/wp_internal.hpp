@@ -24,9 +24,25 @@ enum : uint32_t {
 
 struct GridDev {
   int32_t ndim;
-  int32_t lg[3];  // log2 of the axis lengths (0 on unused axes)
+  int32_t lg[3];  // log2 of the axis lengths (0 on unused axes; power-of-two grids)
   double lo[3], dx[3];
+  int32_t n[3];   // axis lengths (1 on unused axes)
+  int32_t pow2;   // every length a power of two: indices by shifts, else by division
 };
+
+// Indices (i0, i1, i2) of point i of the row-major [n0][n1][n2] grid.
+__device__ __forceinline__ void grid_index(const GridDev &g, int64_t i, int &i0, int &i1, int &i2) {
+  if (g.pow2) {
+    i2 = (int)(i & ((1 << g.lg[2]) - 1));
+    i1 = (int)((i >> g.lg[2]) & ((1 << g.lg[1]) - 1));
+    i0 = (int)(i >> (g.lg[1] + g.lg[2]));
+  } else {
+    i2 = (int)(i % g.n[2]);
+    const int64_t r = i / g.n[2];
+    i1 = (int)(r % g.n[1]);
+    i0 = (int)(r / g.n[1]);
+  }
+}
 
 // Time of a potential evaluation: t = t0 + (step + (step_dev ? *step_dev : 0)) * dt
 // (time by multiplication, never by accumulation).
@@ -40,6 +56,12 @@ struct TimeDev {
 __device__ __forceinline__ double time_of(const TimeDev &T) {
   int64_t n = T.step + (T.step_dev ? *T.step_dev : 0);
   return T.t0 + ((double)n + T.half) * T.dt;
+}
+
+// Time of step s after the first (plus `half` of a step).
+__device__ __forceinline__ double step_time_of(const TimeDev &T, int64_t s, double half) {
+  int64_t n = T.step + s + (T.step_dev ? *T.step_dev : 0);
+  return T.t0 + ((double)n + half) * T.dt;
 }
 
 struct PassArgs {
@@ -109,9 +131,30 @@ struct BatchLaunch {
   int tune;  // kernel variant
 };
 
+// ---- mixed-radix lengths (any 2^a 3^b 5^c 7^d up to kMaxMixed) ----------
+// Stage plan of one line transform (Stockham, radices 2, 3, 4, 5, 7, 8):
+// stage s has radix radix[s], LS = product of the earlier radices, and its
+// twiddles exp(-2 pi i r k/(radix LS)) at twoff[s] + (r-1) LS + k.
+constexpr int kMaxStages = 12;
+constexpr int kMaxMixed = 4096;
+struct GPlan {
+  int32_t nst;
+  int32_t radix[kMaxStages], ls[kMaxStages], twoff[kMaxStages];
+};
+
+// A line pass on a grid with lengths that are not all powers of two.
+struct GPassArgs {
+  PassArgs p;     // as for the power-of-two passes (g.n gives the lengths)
+  int64_t inner;  // product of the lengths after the line axis
+  GPlan plan;     // of the line axis; p.tw holds its stage twiddles
+};
+
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s);
 hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s);
+hipError_t launch_gpass(int prec, const GPassArgs &a, hipStream_t s);
+// 1D solve of any supported mixed length in one workgroup (a.g.n[0] points).
+hipError_t launch_gsolve1d(int prec, const Solve1DArgs &a, const GPlan &plan, hipStream_t s);
 hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<double> *f0,
                            const cx<double> *f1, const cx<double> *f2, hipStream_t s);
 hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src, int64_t count,

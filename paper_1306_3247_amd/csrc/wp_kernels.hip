@@ -89,11 +89,6 @@ int pass_tile(int prec, int lgN, bool strided, int kind, int tune) {
 // 1D solve in one workgroup: the whole line stays in registers and LDS for
 // all steps; HBM is read once and written once.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double step_time(const TimeDev &T, int64_t s, double half) {
-  int64_t n = T.step + s + (T.step_dev ? *T.step_dev : 0);
-  return T.t0 + ((double)n + half) * T.dt;
-}
-
 template <class S, class R, int N>
 __device__ __forceinline__ void solve1d_body(const Solve1DArgs &a, int64_t nsteps) {
   using T = typename storage<S>::type;
@@ -141,11 +136,11 @@ __device__ __forceinline__ void solve1d_body(const Solve1DArgs &a, int64_t nstep
   const int64_t ns = nsteps;
   if (!kvk) {
     for (int64_t s = 0; s < ns; ++s) {
-      if (s == 0) apply_v(step_time(a.time, 0, 0.0), a.vtau_half);
+      if (s == 0) apply_v(step_time_of(a.time, 0, 0.0), a.vtau_half);
       line_fft<N, VPT, false>(v, t, a.tw, lds);
       apply_k(false);
       line_fft<N, VPT, true>(v, t, a.tw, lds);
-      apply_v(step_time(a.time, s + 1, 0.0), s + 1 == ns ? a.vtau_half : a.vtau_full);
+      apply_v(step_time_of(a.time, s + 1, 0.0), s + 1 == ns ? a.vtau_half : a.vtau_full);
     }
   } else if (ns > 0) {
     // K/2 V K/2 with consecutive kinetic halves merged into full steps.
@@ -153,7 +148,7 @@ __device__ __forceinline__ void solve1d_body(const Solve1DArgs &a, int64_t nstep
     apply_k(true);
     for (int64_t s = 0; s < ns; ++s) {
       line_fft<N, VPT, true>(v, t, a.tw, lds);
-      apply_v(step_time(a.time, s, 0.5), a.vtau_full);
+      apply_v(step_time_of(a.time, s, 0.5), a.vtau_full);
       line_fft<N, VPT, false>(v, t, a.tw, lds);
       if (s + 1 == ns) {
         apply_k(true);
@@ -243,7 +238,7 @@ __global__ void coef_kernel(PotDev p, TimeDev T, int count, double *out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count * CO_COUNT) return;
   const int j = i / CO_COUNT, w = i % CO_COUNT;
-  out[i] = wave_value(p.w[w], step_time(T, j, T.half));
+  out[i] = wave_value(p.w[w], step_time_of(T, j, T.half));
 }
 
 hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, double *out, hipStream_t s) {
@@ -284,11 +279,10 @@ __global__ void gaussian_kernel(void *out, GridDev g, const cx<double> *f0, cons
                                 const cx<double> *f2, int64_t total) {
   using T = typename storage<R>::type;
   T *psi = (T *)out;
-  const int m1 = (1 << g.lg[1]) - 1, m2 = (1 << g.lg[2]) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int i2 = (int)(i & m2), i1 = (int)((i >> g.lg[2]) & m1);
-    const int64_t i0 = i >> (g.lg[1] + g.lg[2]);
+    int i0, i1, i2;
+    grid_index(g, i, i0, i1, i2);
     const cx<double> f = cmul(cmul(f0[i0], f1[i1]), f2[i2]);
     store_from(psi + i, f);
   }
@@ -303,7 +297,7 @@ static unsigned grid_blocks(int64_t total, int threads) {
 
 hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<double> *f0,
                            const cx<double> *f1, const cx<double> *f2, hipStream_t s) {
-  const int64_t total = (int64_t)1 << (g.lg[0] + g.lg[1] + g.lg[2]);
+  const int64_t total = (int64_t)g.n[0] * g.n[1] * g.n[2];
   const unsigned b = grid_blocks(total, 256);
   if (prec == 2) hipLaunchKernelGGL(gaussian_kernel<double>, dim3(b), dim3(256), 0, s, psi, g, f0, f1, f2, total);
   else hipLaunchKernelGGL(gaussian_kernel<float>, dim3(b), dim3(256), 0, s, psi, g, f0, f1, f2, total);
@@ -349,14 +343,14 @@ __global__ void __launch_bounds__(kObsThreads) obs_kernel(ObsArgs a) {
   __syncthreads();
   const T *psi = (const T *)a.psi;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int m1 = (1 << a.g.lg[1]) - 1, m2 = (1 << a.g.lg[2]) - 1;
+
   for (int64_t i = (int64_t)blockIdx.x * kObsThreads + tid; i < a.total;
        i += (int64_t)gridDim.x * kObsThreads) {
     const T p = psi[i];
     const double pr = p.x, pi = p.y;
     const double w = pr * pr + pi * pi;
-    const int i2 = (int)(i & m2), i1 = (int)((i >> a.g.lg[2]) & m1);
-    const int i0 = (int)(i >> (a.g.lg[1] + a.g.lg[2]));
+    int i0, i1, i2;
+    grid_index(a.g, i, i0, i1, i2);
     if (a.kinetic && a.split_h) {
       // split 1D: point k1*n2 + k2 holds bin k1 + n1*k2
       const int lg2 = a.g.lg[0] - a.split_h;

@@ -76,7 +76,7 @@ def test_state_and_workspace_bytes(lib):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(ndim=0), dict(ndim=4), dict(n=[6, 16, 4]), dict(n=[1, 16, 4]), dict(lo=[1.0, -1, -1]),
+    dict(ndim=0), dict(ndim=4), dict(n=[1, 16, 4]), dict(lo=[1.0, -1, -1]),
     dict(mass=0.0), dict(mass=-1.0), dict(hbar=0.0), dict(dt=0.0), dict(dt=float("nan")),
     dict(ndim=2),  # unused third axis must have n = 1
 ])
@@ -104,3 +104,20 @@ def test_single_hip_runtime(lib):
     from paper_1306_3247_amd import sim
 
     assert len(sim._hip_runtimes()) == 1
+
+
+def test_mixed_lengths_accepted_and_limited(lib):
+    """Lengths with prime factors 2, 3, 5, 7 up to 4096 are valid descriptors;
+    other factors and longer mixed axes are refused before any device work."""
+    rc, b = _state_bytes(lib, _desc(_grid(n=[6, 10, 14]), "c64"))
+    assert rc == 0 and b == 6 * 10 * 14 * 8
+    pot = sim_potential()
+    for n, want in (([11, 16, 4], -4), ([4200, 2, 2], -4), ([13, 5, 7], -4)):
+        out = C.c_void_p()
+        assert lib.wp_create(C.byref(_desc(_grid(n=n))), C.byref(pot), None, C.byref(out)) == want, n
+
+
+def sim_potential():
+    from paper_1306_3247_amd import sim, workloads as W
+
+    return sim.potential_desc(W.Potential())

@@ -103,6 +103,75 @@ def test_1d_split_nonseparable(S, W, oracle_mod, v0, precision):
     assert rel_l2(got, ref) <= TOL[precision]
 
 
+# Mixed-radix lengths (prime factors 2, 3, 5, 7): every radix and several
+# factor orders, odd lengths, up to the 4096-point limit.
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("order", ["vkv", "kvk"])
+@pytest.mark.parametrize("n", [3, 5, 6, 7, 12, 15, 49, 105, 360, 2520, 3087, 4000])
+def test_1d_mixed_random_state(S, W, oracle_mod, n, order, precision):
+    prob = W.driven_ho_1d(n=n, steps=6, precision=precision)
+    psi0 = W.random_state((n,), seed=n + 3)
+    psi0 /= np.linalg.norm(psi0)
+    got, ref, _ = run_both(S, oracle_mod, prob, psi0, order)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
+@pytest.mark.parametrize("order", ["vkv", "kvk"])
+@pytest.mark.parametrize("shape", [(6, 10), (15, 64), (64, 21), (360, 120), (7, 49), (3, 4096)])
+def test_2d_mixed_random_state(S, W, oracle_mod, shape, order, precision):
+    prob = W.modulated_trap_2d(n=4, steps=4, precision=precision)
+    prob.grid.n = list(shape)
+    psi0 = W.random_state(shape, seed=5 + sum(shape))
+    psi0 /= np.linalg.norm(psi0)
+    got, ref, _ = run_both(S, oracle_mod, prob, psi0, order)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
+@pytest.mark.parametrize("order", ["vkv", "kvk"])
+@pytest.mark.parametrize("shape", [(6, 10, 14), (3, 5, 7), (30, 24, 20), (16, 9, 32)])
+def test_3d_mixed_random_state(S, W, oracle_mod, shape, order, precision):
+    prob = W.softcore_3d(n=4, steps=3, precision=precision, half_width=6.0)
+    prob.grid.n = list(shape)
+    prob.t0 = 9.0
+    psi0 = W.random_state(shape, seed=11 + sum(shape))
+    psi0 /= np.linalg.norm(psi0)
+    got, ref, _ = run_both(S, oracle_mod, prob, psi0, order)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_mixed_gaussian_physics(S, W, oracle_mod, precision):
+    """A Gaussian in the modulated trap on a 360 x 375 grid (2^3 3^2 5 and
+    3 5^3 points), 200 steps, against the oracle; observables too."""
+    prob = W.modulated_trap_2d(n=4, steps=200, precision=precision, half_width=8.0)
+    prob.grid.n = [360, 375]
+    got, ref, psi0 = run_both(S, oracle_mod, prob)
+    assert rel_l2(got, ref) <= TOL[precision]
+    t = prob.t0 + prob.steps * prob.grid.dt
+    s = S.Simulation(prob.grid, prob.pot, precision)
+    s.set_state(psi0, t0=prob.t0)
+    s.store_reference()
+    s.set_state(ref, t0=t)
+    o = s.observables(S.OBS_ALL_EXT)
+    s.close()
+    want = oracle_all(oracle_mod, prob, ref, t, psi0)
+    tol = 1e-12 if precision == "c128" else 2e-6
+    scale = max(1.0, max(abs(v) for v in want.values()))
+    for k in KEYS:
+        assert abs(o[k] - want[k]) <= tol * scale, (k, o[k], want[k])
+
+
+def test_mixed_batch_rejected(S, W):
+    p = W.modulated_trap_2d(n=4, steps=0, precision="c64")
+    p.grid.n = [6, 10]
+    s = S.from_problem(p)
+    with pytest.raises(S.WavepacketError):
+        S.Batch([s])
+    s.close()
+
+
 @pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
 def test_1d_morse(S, W, oracle_mod, precision):
     prob = morse_dipole_1d(W, 512, 100, precision)
