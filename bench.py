@@ -320,7 +320,8 @@ def main() -> int:
     prof = s32.profile_propagate(args.profile_steps)
     state_bytes = S.state_bytes(prob.grid, "c64")
     alg_bytes = 2 * state_bytes
-    timed = {k: s32.time_pass(k, args.pass_reps) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
+    # best of three rounds per class (the first launches after an idle spell run slower)
+    timed = {k: min(s32.time_pass(k, args.pass_reps) for _ in range(3)) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
     lg = int(np.log2(args.n))
     variant = {"axis0": S.tune_get(False, "c64", lg, True, "potential"),
                "mid_fwd": S.tune_get(False, "c64", lg, True, "fft"),

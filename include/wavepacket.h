@@ -275,17 +275,34 @@ wp_status wp_time_pass(wp_sim *sim, int32_t kind, uint32_t reps, double *ms);
  * entries never tuned run variant 0.  Results do not depend on the variant
  * (the same arithmetic in the same order), only the speed does. */
 #define WP_TUNE_VARIANTS 4
+#define WP_TUNE_SLAB_CHOICES 8
 
 /* Time every variant of the handle's line passes ([0] potential pass of the
  * first axis, [1] middle-axis FFT (3D), [2] kinetic pass of the last axis)
  * over `reps` back-to-back launches each, on a device copy of the state
  * (the state itself is unchanged; one state-sized scratch buffer is
- * allocated on first use), and store the fastest in the table.  ms, if not
- * NULL, receives 3 x WP_TUNE_VARIANTS average milliseconds (NaN for
- * variants not tried).  Passes built afterwards by any handle use the
- * table; a 1D grid solved in one workgroup has nothing to tune (WP_OK).
- * Synchronises.  WP_EINVAL: reps not in 1..10000. */
+ * allocated on first use), and store the fastest in the table; on 3D
+ * power-of-two grids then time whole steps with 1, 2, 4, ... x slabs (see
+ * wp_set_slabs) and keep the fastest count for this handle.  ms, if not
+ * NULL, receives 3 x WP_TUNE_VARIANTS average milliseconds per launch
+ * followed by WP_TUNE_SLAB_CHOICES milliseconds per step for 2^0 .. 2^7
+ * slabs (NaN where not tried).  Passes built afterwards by any handle use
+ * the table; a 1D grid solved in one workgroup and mixed-length grids have
+ * nothing to tune (WP_OK).  Synchronises.  WP_EINVAL: reps not in
+ * 1..10000. */
 wp_status wp_autotune(wp_sim *sim, uint32_t reps, double *ms);
+
+/* 3D power-of-two grids: run the middle passes of a step (forward FFT of
+ * the middle axis, kinetic pass of the last axis, inverse FFT of the
+ * middle axis) on `count` slabs of consecutive x planes, one slab after the
+ * other, so that a slab stays in the GPU's memory-side cache between its
+ * three passes and only the first pass reads it from HBM.  The arithmetic
+ * is the same (results are bit-identical for every count).  count: a power
+ * of two up to n0; 1 for other grids.  The default keeps slabs at most
+ * 256 MiB.  WP_EINVAL otherwise. */
+wp_status wp_set_slabs(wp_sim *sim, uint32_t count);
+/* The handle's slab count (0 for a NULL handle). */
+uint32_t wp_get_slabs(const wp_sim *sim);
 
 /* The table entry for one pass shape (see above); *tune receives 0 for
  * shapes never tuned. */

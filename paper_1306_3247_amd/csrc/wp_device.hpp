@@ -260,15 +260,14 @@ __device__ __forceinline__ cx<double> expmi_quarter(double r) {
   return {fma(-pc, r2, 1.0), -fma(ps * r2, r, r)};
 }
 
-// |theta| <= 1/16: the series to r^9 and r^10 (next terms below 1e-20).
+// |theta| <= 1/16: the series to r^7 and r^8 (the next terms, r^9/9! and
+// r^10/10!, are below 4e-17 and 3e-19).
 __device__ __forceinline__ cx<double> expmi_tiny(double r) {
   const double r2 = r * r;
-  double ps = inv_fact<9>::value;
-  ps = fma(ps, r2, -inv_fact<7>::value);
+  double ps = -inv_fact<7>::value;
   ps = fma(ps, r2, inv_fact<5>::value);
   ps = fma(ps, r2, -inv_fact<3>::value);
-  double pc = -inv_fact<10>::value;
-  pc = fma(pc, r2, inv_fact<8>::value);
+  double pc = inv_fact<8>::value;
   pc = fma(pc, r2, -inv_fact<6>::value);
   pc = fma(pc, r2, inv_fact<4>::value);
   pc = fma(pc, r2, -inv_fact<2>::value);
@@ -313,6 +312,21 @@ __device__ __forceinline__ cx<double> expmi_taylor(double th) {
   const double cosv = (q == 1 || q == 2) ? -c1 : c1;
   const double sinv = (q >= 2) ? -s1 : s1;
   return {cosv, -sinv};
+}
+
+// 1/sqrt(q) for q > 0: the FP32 estimate refined by one FP64 Newton step
+// (relative error below 1e-13), with the FP64 library call for lanes outside
+// the FP32 range (taken by the whole wavefront if any lane needs it).
+__device__ __forceinline__ double rsqrt_fast(double q) {
+  const bool in_range = q > 1e-30 && q < 1e30;
+  double r;
+  if (__all(in_range)) {
+    r = (double)__frsqrt_rn((float)q);
+    r = r * fma(-0.5 * q * r, r, 1.5);
+  } else {
+    r = rsqrt(q);
+  }
+  return r;
 }
 
 // exp(-i theta) choosing, for the whole wavefront at once (the branches stay

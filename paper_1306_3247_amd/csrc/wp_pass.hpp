@@ -207,7 +207,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
         const double x = lo + (double)(((int64_t)(t + L * u) << lg2) + j2) * dx;
         double th = cc + x * fma(cb, x, ca);
         if (kind == 1) {
-          th -= cs * p0 * rsqrt(fma(x, x, p1));
+          th -= cs * p0 * rsqrt_fast(fma(x, x, p1));
         } else if (kind == 2) {
           const double e = 1.0 - exp(-p1 * (x - p2));
           th += cs * p0 * e * e;
@@ -271,7 +271,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
         const double x = lo + (double)(t + L * u) * dx;
         double th = th_line + x * fma(cb, x, ca);
         if (kind == 1) {
-          th -= cs * p0 * rsqrt(fma(x, x, r2off));
+          th -= cs * p0 * rsqrt_fast(fma(x, x, r2off));
         } else {
           const double e = 1.0 - exp(-p1 * (x - p2));
           th += cs * p0 * e * e;

@@ -92,6 +92,7 @@ def _load() -> C.CDLL:
         "wp_store_reference": [vp],
         "wp_time_pass": [vp, C.c_int32, C.c_uint32, P(d)],
         "wp_autotune": [vp, C.c_uint32, P(d)],
+        "wp_set_slabs": [vp, C.c_uint32],
         "wp_batch_autotune": [vp, C.c_uint32],
         "wp_tune_get": [C.c_int32] * 5 + [P(C.c_int32)],
         "wp_tune_set": [C.c_int32] * 6,
@@ -114,6 +115,8 @@ def _load() -> C.CDLL:
     L.wp_batch_last_error.restype = C.c_char_p
     L.wp_tune_clear.argtypes = []
     L.wp_tune_clear.restype = None
+    L.wp_get_slabs.argtypes = [vp]
+    L.wp_get_slabs.restype = C.c_uint32
     return L
 
 
@@ -174,6 +177,7 @@ def workspace_bytes(grid, precision: str) -> int:
 
 PASS_KIND_IDS = {"fft": 0, "potential": 1, "kinetic": 2, "split_potential": 3, "split_kinetic": 4}
 TUNE_VARIANTS = 4
+TUNE_SLAB_CHOICES = 8
 
 
 def tune_get(batched: bool, precision: str, lg_n: int, strided: bool, kind: str) -> int:
@@ -335,7 +339,7 @@ class Simulation:
     def autotune(self, reps: int = 10) -> dict:
         """Time every kernel variant of this grid's line passes and store the
         fastest in the tuning table; returns {class: {variant: ms}}."""
-        ms = (C.c_double * (3 * TUNE_VARIANTS))()
+        ms = (C.c_double * (3 * TUNE_VARIANTS + TUNE_SLAB_CHOICES))()
         self._check(lib.wp_autotune(self._h, int(reps), ms), "wp_autotune")
         out = {}
         for c, name in enumerate(self.TUNE_CLASSES):
@@ -343,7 +347,18 @@ class Simulation:
                    if ms[c * TUNE_VARIANTS + v] == ms[c * TUNE_VARIANTS + v]}
             if row:
                 out[name] = row
+        slabs = {1 << k: ms[3 * TUNE_VARIANTS + k] for k in range(TUNE_SLAB_CHOICES)
+                 if ms[3 * TUNE_VARIANTS + k] == ms[3 * TUNE_VARIANTS + k]}
+        if slabs:
+            out["slabs"] = slabs
         return out
+
+    def set_slabs(self, count: int) -> None:
+        """x slabs of the middle passes of a 3D step (see wp_set_slabs)."""
+        self._check(lib.wp_set_slabs(self._h, int(count)), "wp_set_slabs")
+
+    def slabs(self) -> int:
+        return int(lib.wp_get_slabs(self._h))
 
     def state_ptr(self) -> int:
         return lib.wp_state_ptr(self._h)

@@ -76,9 +76,11 @@ def test_autotune_picks_fastest_and_keeps_state(S, W, precision):
     times = s.autotune(reps=5)
     after = s.get_state("c128")
     assert np.array_equal(before, after)
-    assert set(times) == {"axis0", "mid", "last"}
+    assert set(times) == {"axis0", "mid", "last", "slabs"}
     expect = {"axis0": (True, "potential"), "mid": (True, "fft"), "last": (False, "kinetic")}
     for cls, row in times.items():
+        if cls == "slabs":
+            continue
         assert row and all(ms > 0 for ms in row.values())
         strided, kind = expect[cls]
         chosen = S.tune_get(False, precision, 7, strided, kind)
@@ -128,3 +130,46 @@ def test_tune_set_rejects_out_of_range(S):
         S.tune_set(False, "c64", 9, True, "potential", 4)
     with pytest.raises(S.WavepacketError):
         S.tune_set(False, "c64", 13, True, "potential", 1)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_slabs_bit_identical(S, W, precision):
+    """The middle passes of a 3D step run slab by slab: the same arithmetic
+    for every slab count, in both orders."""
+    for order in ("vkv", "kvk"):
+        prob = W.softcore_3d(n=64, steps=0, precision=precision, half_width=5.0)
+        prob.t0 = 9.0
+        out = []
+        for count in (1, 2, 8, 64):
+            s = S.from_problem(prob, order=order)
+            s.set_slabs(count)
+            assert s.slabs() == count
+            s.propagate(5)
+            out.append(s.get_state("c128"))
+            s.close()
+        for o in out[1:]:
+            assert np.array_equal(o, out[0]), order
+
+
+def test_slabs_rejected_where_meaningless(S, W):
+    p2 = W.modulated_trap_2d(n=64, steps=0, precision="c64")
+    s = S.from_problem(p2)
+    s.set_slabs(1)
+    with pytest.raises(S.WavepacketError):
+        s.set_slabs(2)
+    s.close()
+    p3 = W.softcore_3d(n=16, steps=0, precision="c64", half_width=3.0)
+    s = S.from_problem(p3)
+    for bad in (3, 32):
+        with pytest.raises(S.WavepacketError):
+            s.set_slabs(bad)
+    s.close()
+
+
+def test_autotune_picks_a_slab_count(S, W):
+    prob = W.softcore_3d(n=128, steps=0, precision="c64", half_width=10.0)
+    s = S.from_problem(prob)
+    times = s.autotune(reps=4)
+    assert "slabs" in times and set(times["slabs"]) == {1 << k for k in range(8)}
+    assert s.slabs() == min(times["slabs"], key=times["slabs"].get)
+    s.close()
