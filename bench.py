@@ -148,8 +148,14 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
     import torch
 
     kw = dict(budget_bytes=int(budget_gib * (1 << 30)), tick_steps=tick, graph_steps=graph_steps)
+
+    def progress(label):
+        def show(done, total, t):
+            if done % 100 == 0 or done == total:
+                print(f"serving {label}: {done}/{total} results, {t:.1f} s", file=sys.stderr, flush=True)
+        return show
     cap_reqs = W.serving_stream(cap_count, float("inf"), seed=1306)
-    cap_rep = V.Server(**kw).run(cap_reqs)
+    cap_rep = V.Server(**kw).run(cap_reqs, progress("closed loop"))
     cap = cap_rep.summary()
     # Capacity in requests/s: the saturated throughput in site-steps/s over
     # the mean work of a request of this mix (the mean over a long sample is
@@ -161,7 +167,7 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
     for i, f in enumerate(rates):
         reqs = W.serving_stream(warm + count, f * C, seed=1306 + 1 + i)
         keep = {r.rid for r in reqs[warm:warm + 3]} if i == 0 else False
-        rep = V.Server(keep_results=keep, **kw).run(reqs)
+        rep = V.Server(keep_results=keep, **kw).run(reqs, progress(f"rate {f:g} C"))
         s = rep.summary(first_rid=warm)
         s.update({"rate_frac": f, "rate_hz": f * C})
         runs.append(s)

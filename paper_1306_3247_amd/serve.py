@@ -164,9 +164,11 @@ class Server:
         job.host = None
 
     # -- the loop ----------------------------------------------------------
-    def run(self, requests) -> Report:
+    def run(self, requests, progress=None) -> Report:
         """Serve `requests` (objects with .rid, .arrival in seconds, .problem),
-        replaying their arrival times against the wall clock."""
+        replaying their arrival times against the wall clock.  progress, if
+        given, is called as progress(finished, total, seconds) whenever a
+        result has reached the host."""
         torch = self.torch
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         served = [Served(r.rid, float(r.arrival), steps=int(r.problem.steps),
@@ -180,6 +182,7 @@ class Server:
         batch, batch_key = None, None
         used = peak = 0
         ticks = batches = flushes = 0
+        finished = 0
         nxt = 0
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
@@ -214,6 +217,9 @@ class Server:
                 if j.copy_event.query():
                     self._finish(j, clock())
                     grave_sims.append(j)
+                    finished += 1
+                    if progress is not None:
+                        progress(finished, len(reqs), clock())
                 else:
                     still.append(j)
             retiring = still

@@ -121,3 +121,30 @@ def sim_potential():
     from paper_1306_3247_amd import sim, workloads as W
 
     return sim.potential_desc(W.Potential())
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    """No silent fallback: if the compiled library is absent the binding
+    refuses to load."""
+    import importlib.util
+    import os as _os
+
+    spec = importlib.util.spec_from_file_location(
+        "sim_probe", _os.path.join(_os.path.dirname(LIB), "sim.py"))
+    mod = importlib.util.module_from_spec(spec)
+    real_exists = _os.path.exists
+    monkeypatch.setattr(_os.path, "exists", lambda p: False if p.endswith("libwavepacket.so") else real_exists(p))
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)
+
+
+def test_tune_table_host_side(lib):
+    """The tuning table is host state: set, read back, clear (no device)."""
+    out = C.c_int32()
+    assert lib.wp_tune_set(0, 1, 9, 1, 1, 2) == 0
+    assert lib.wp_tune_get(0, 1, 9, 1, 1, C.byref(out)) == 0 and out.value == 2
+    assert lib.wp_tune_get(1, 1, 9, 1, 1, C.byref(out)) == 0 and out.value == 0  # batched entry separate
+    assert lib.wp_tune_set(0, 1, 9, 1, 1, 4) == -1
+    assert lib.wp_tune_set(0, 9, 9, 1, 1, 1) == -1
+    lib.wp_tune_clear()
+    assert lib.wp_tune_get(0, 1, 9, 1, 1, C.byref(out)) == 0 and out.value == 0

@@ -106,3 +106,18 @@ def test_batch_rejects_bad_input(S, W):
     with pytest.raises(S.WavepacketError):
         S.Batch([s])
     s.close()
+
+
+def test_zero_steps_are_no_ops(S, W):
+    """propagate(0) leaves state, time and counters alone, alone and batched."""
+    p = W.driven_trap(2, 64, 0.1, 1.0, [0.5, 0.0], [0.0, 0.3], steps=0, precision="c64")
+    s = S.from_problem(p)
+    s.propagate(3)
+    before = s.get_state("c128")
+    s.propagate(0)
+    b = S.Batch([s], graph_steps=4)
+    b.propagate(0)
+    b.close()
+    assert np.array_equal(s.get_state("c128"), before)
+    assert s.time() == (p.t0 + 3 * p.grid.dt, 3)
+    s.close()
