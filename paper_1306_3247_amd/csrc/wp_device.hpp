@@ -391,13 +391,6 @@ __device__ __forceinline__ double v0_value(const PotDev &p, double x0, double x1
   return 0.0;
 }
 
-// exp(-i theta) in FP64.
-__device__ __forceinline__ cx<double> expmi(double th) {
-  double s, c;
-  sincos(th, &s, &c);
-  return {c, -s};
-}
-
 // ---------------------------------------------------------------------------
 // storage conversions
 // ---------------------------------------------------------------------------

@@ -181,7 +181,7 @@ __device__ __forceinline__ void gpass_body(const GPassArgs &ga, int kind) {
       j = e - tau * N;
     }
   };
-  cx<double> *A = s_buf, *B = s_buf + kGBuf;
+  cx<double> *A = s_buf;
   for (int e = threadIdx.x; e < tile * N; e += kGThreads) {
     int tau, j;
     which(e, tau, j);

@@ -157,8 +157,6 @@ hipError_t launch_gpass(int prec, const GPassArgs &a, hipStream_t s);
 hipError_t launch_gsolve1d(int prec, const Solve1DArgs &a, const GPlan &plan, hipStream_t s);
 hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<double> *f0,
                            const cx<double> *f1, const cx<double> *f2, hipStream_t s);
-hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src, int64_t count,
-                          hipStream_t s);
 hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s);
 // <phi|psi> without dV: out8[0], out8[1] (precisions 1 = complex64, 2 = complex128).
 hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int blocks,

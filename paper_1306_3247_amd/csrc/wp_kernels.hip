@@ -304,30 +304,6 @@ hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<doubl
   return hipGetLastError();
 }
 
-template <class D, class Sx>
-__global__ void convert_kernel(D *dst, const Sx *src, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    Sx v = src[i];
-    D w;
-    w.x = v.x;
-    w.y = v.y;
-    dst[i] = w;
-  }
-}
-
-hipError_t launch_convert(int to_prec, void *dst, int from_prec, const void *src, int64_t count,
-                          hipStream_t s) {
-  const unsigned b = grid_blocks(count, 256);
-  if (to_prec == 2 && from_prec == 1)
-    hipLaunchKernelGGL((convert_kernel<double2, float2>), dim3(b), dim3(256), 0, s, (double2 *)dst, (const float2 *)src, count);
-  else if (to_prec == 1 && from_prec == 2)
-    hipLaunchKernelGGL((convert_kernel<float2, double2>), dim3(b), dim3(256), 0, s, (float2 *)dst, (const double2 *)src, count);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // observables: deterministic FP64 reductions.  Every block sums a fixed set
 // of points (grid-stride order with a fixed grid), reduces in LDS by a fixed

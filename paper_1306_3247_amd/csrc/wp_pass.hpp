@@ -75,7 +75,12 @@ struct pass_cfg {
   // Waves per SIMD the register allocation must leave room for: two
   // workgroups per CU (at most 128 VGPRs for 512-thread workgroups); three
   // 256-thread workgroups in variant 2.
-  static constexpr int WAVES_EU = (TUNE & 2) ? imax(1, imin(4, 3 * THREADS / 256)) : imax(1, imin(4, THREADS / 128));
+  static constexpr int WAVES_TARGET = (TUNE & 2) ? imax(1, imin(4, 3 * THREADS / 256)) : imax(1, imin(4, THREADS / 128));
+  // No more waves than the LDS of a CU (160 KiB) lets in, so that the
+  // register budget is not cut for occupancy that cannot happen.
+  static constexpr int LDS_BYTES = DATA_BYTES + (TW_LDS ? TW_BYTES : 0) + TAB_BYTES + 64;
+  static constexpr int WAVES_LDS = imax(1, (163840 / LDS_BYTES) * ((THREADS + 63) / 64) / 4);
+  static constexpr int WAVES_EU = imin(WAVES_TARGET, WAVES_LDS);
 };
 
 __device__ __forceinline__ void decode_line(const GridDev &g, int axis, int64_t o, int64_t c, int idx[3]) {
