@@ -169,11 +169,11 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
 wp_status wp_destroy(wp_sim *sim);
 
 /* Use caller-owned device memory `dev_psi` (at least wp_state_bytes, 16-byte
- * aligned) as the state from now on; a state buffer the library allocated
- * before is freed.
- * The caller keeps ownership and must keep the memory alive until
- * wp_destroy.  The content is not changed.  Errors: WP_EINVAL (NULL, too
- * small or misaligned). */
+ * aligned) as the state from now on; work queued afterwards uses it.  A
+ * state buffer the library allocated before is freed after waiting for the
+ * handle's stream (only then does the call synchronise).  The caller keeps
+ * ownership and must keep the memory alive until wp_destroy.  The content
+ * is not changed.  Errors: WP_EINVAL (NULL, too small or misaligned). */
 wp_status wp_bind_state(wp_sim *sim, void *dev_psi, uint64_t bytes);
 
 /* Device pointer of the current state (library-owned or bound). */

@@ -541,9 +541,12 @@ wp_status wp_bind_state(wp_sim *s, void *dev_psi, uint64_t bytes) {
   if (bytes < s->psi_bytes) return fail(s, WP_EINVAL, "bind_state: buffer smaller than the state");
   if (((uintptr_t)dev_psi & 15) != 0) return fail(s, WP_EINVAL, "bind_state: buffer not 16-byte aligned");
   (void)hipSetDevice(s->device);
-  hipError_t e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(s, e, "bind_state");
-  if (s->psi_owned && s->psi) (void)hipFree(s->psi);
+  if (s->psi_owned && s->psi) {
+    // the library's own buffer is freed once no queued work can use it
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "bind_state");
+    (void)hipFree(s->psi);
+  }
   s->psi = dev_psi;
   s->psi_owned = false;
   s->err.clear();
