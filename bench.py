@@ -228,7 +228,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=512, help="points per axis")
-    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=10, help="steps of the per-launch event breakdown")
     ap.add_argument("--pass-reps", type=int, default=20, help="back-to-back launches per timed pass class")
     ap.add_argument("--no-autotune", action="store_true", help="run the default kernel variants")
     ap.add_argument("--tune-reps", type=int, default=10)
@@ -317,31 +317,31 @@ def main() -> int:
             sx.close()
         s64.close()
 
-    # Roofline of the dominant kernel: every pass reads and writes the whole
-    # state once, so its algorithmic bytes per launch are 2 * state bytes.
-    # Each steady-step pass class is timed over back-to-back launches between
-    # one event pair on the handle's stream (an event pair around every
-    # launch, as in the per-step breakdown below, adds its own delay to each
-    # launch); the class with the longest launch dominates a step.
-    prof = s32.profile_propagate(args.profile_steps)
+    # Roofline of the dominant kernel.  Every pass reads and writes the whole
+    # state once: 2 x state bytes per launch over the whole grid.  Each pass
+    # class is launched back to back on the handle's stream between one
+    # event pair (wp_time_pass), best of three rounds; the slowest class
+    # dominates a step.  An event pair around single launches inside a step
+    # (wp_profile_propagate, kept as passes_event_per_launch) delays each
+    # bracketed launch by up to ~0.1 ms, so it is not used for the roofline.
     state_bytes = S.state_bytes(prob.grid, "c64")
     alg_bytes = 2 * state_bytes
-    # best of three rounds per class (the first launches after an idle spell run slower)
     timed = {k: min(s32.time_pass(k, args.pass_reps) for _ in range(3)) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
+    kind, avg_ms = max(timed.items(), key=lambda kv: kv[1])
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     lg = int(np.log2(args.n))
     variant = {"axis0": S.tune_get(False, "c64", lg, True, "potential"),
                "mid_fwd": S.tune_get(False, "c64", lg, True, "fft"),
                "mid_inv": S.tune_get(False, "c64", lg, True, "fft"),
                "last": S.tune_get(False, "c64", lg, False, "kinetic")}
-    kind, avg_ms = max(timed.items(), key=lambda kv: kv[1])
-    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    prof = s32.profile_propagate(args.profile_steps)
     out["roofline"] = {"bound": "hbm", "kernel": f"pass:{kind}", "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": traffic_for(kind, workload, variant[kind]), "variant": variant[kind],
-                       "avg_launch_ms": round(avg_ms, 4),
-                       "alg_bytes_per_launch": alg_bytes, "reps": args.pass_reps,
-                       "passes": {k: {"avg_ms": round(m, 4),
-                                      "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)} for k, m in timed.items()},
+                       "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": alg_bytes, "reps": args.pass_reps,
+                       "slabs": s32.slabs(),
+                       "passes": {k: {"avg_ms": round(m, 4), "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)}
+                                  for k, m in timed.items()},
                        "passes_event_per_launch": {k: {"launches": c, "avg_ms": round(m / c, 4)}
                                                    for k, (c, m) in prof.items()}}
     # Whole-step view against the 4-pass byte model (64 B per site-step).

@@ -783,7 +783,7 @@ wp_status wp_propagate(wp_sim *s, uint64_t nsteps) {
   return WP_OK;
 }
 
-wp_status wp_profile_propagate(wp_sim *s, uint64_t nsteps, double *ms, uint64_t *count) {
+wp_status wp_profile_propagate(wp_sim *s, uint64_t nsteps, uint32_t kinds, double *ms, uint64_t *count) {
   if (!s) return WP_EINVAL;
   if (!ms || !count) return fail(s, WP_EINVAL, "profile_propagate: NULL output");
   if (nsteps == 0 || nsteps > 100000) return fail(s, WP_EINVAL, "profile_propagate: nsteps must be in 1..100000");
@@ -797,6 +797,7 @@ wp_status wp_profile_propagate(wp_sim *s, uint64_t nsteps, double *ms, uint64_t 
   // so that the host never waits between launches.
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
   hipError_t e = run_schedule(s, nsteps, [&](int kind, auto &&fn) {
+    if (!((kinds >> kind) & 1u)) return fn();
     hipEvent_t a, b;
     hipError_t r = hipEventCreate(&a);
     if (r != hipSuccess) return r;

@@ -88,7 +88,7 @@ def _load() -> C.CDLL:
         "wp_observables": [vp, C.c_uint32, P(d)],
         "wp_get_time": [vp, P(d), P(u64)],
         "wp_synchronize": [vp],
-        "wp_profile_propagate": [vp, u64, P(d), P(u64)],
+        "wp_profile_propagate": [vp, u64, C.c_uint32, P(d), P(u64)],
         "wp_store_reference": [vp],
         "wp_time_pass": [vp, C.c_int32, C.c_uint32, P(d)],
         "wp_autotune": [vp, C.c_uint32, P(d)],
@@ -318,12 +318,14 @@ class Simulation:
 
     PASS_KINDS = ("solve1d", "axis0", "mid_fwd", "last", "mid_inv", "edge", "coef")
 
-    def profile_propagate(self, nsteps: int) -> dict:
-        """Propagate with a device-timed event pair around every kernel;
-        returns {kind: (launches, total_ms)} for the kinds that ran."""
+    def profile_propagate(self, nsteps: int, kinds=None) -> dict:
+        """Propagate with a device-timed event pair around every kernel of
+        the given classes (names from PASS_KINDS; all by default); returns
+        {kind: (launches, total_ms)} for the bracketed kinds that ran."""
+        mask = 0xFFFFFFFF if kinds is None else sum(1 << self.PASS_KINDS.index(k) for k in kinds)
         ms = (C.c_double * 8)()
         cnt = (C.c_uint64 * 8)()
-        self._check(lib.wp_profile_propagate(self._h, int(nsteps), ms, cnt), "wp_profile_propagate")
+        self._check(lib.wp_profile_propagate(self._h, int(nsteps), mask, ms, cnt), "wp_profile_propagate")
         return {k: (cnt[i], ms[i]) for i, k in enumerate(self.PASS_KINDS) if cnt[i]}
 
     def time_pass(self, kind: str, reps: int = 20) -> float:
