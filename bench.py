@@ -205,7 +205,11 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
             "accuracy_sample": [r.problem.name for r, _ in kept]}
 
 
-def cpu_baseline(prob, budget_s: float):
+def cpu_baseline(S, prob, budget_s: float):
+    """The oracle on the host cores over a bounded sample of whole steps of
+    the workload; the GPU FP32 and FP64 states after the same steps from the
+    same start are compared with the oracle's (the run's error against the
+    FP64 oracle at full size)."""
     import oracle
 
     g = prob.grid
@@ -216,10 +220,21 @@ def cpu_baseline(prob, budget_s: float):
         psi = oracle.propagate(g, prob.pot, psi, 1, t0=prob.t0, n0=steps)
         elapsed += time.perf_counter() - t0
         steps += 1
-    return {"value": g.points() * steps / elapsed, "unit": "site-steps/s", "cores": oracle.num_threads(),
+    base = {"value": g.points() * steps / elapsed, "unit": "site-steps/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"{steps} step(s) of the same {'x'.join(map(str, g.shape()))} workload in FP64 "
                       f"from the Gaussian start, {elapsed:.1f} s wall"}
+    parity = {"steps": steps, "grid": list(g.shape())}
+    ref_norm = float(np.linalg.norm(psi))
+    for prec, key in (("c64", "rel_l2_fp32_vs_oracle"), ("c128", "rel_l2_fp64_vs_oracle")):
+        s = S.from_problem(prob, precision=prec)
+        s.propagate(steps)
+        got = s.get_state("c128")
+        s.close()
+        got -= psi
+        parity[key] = float(np.linalg.norm(got)) / ref_norm
+        del got
+    return base, parity
 
 
 def main() -> int:
@@ -361,7 +376,8 @@ def main() -> int:
                                      args.serve_capacity_requests, args.serve_tick, args.serve_graph_steps,
                                      args.serve_budget_gib, 20)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W.softcore_3d(n=args.n, precision="c128"), args.cpu_seconds)
+        out["cpu_baseline"], out["oracle_parity"] = cpu_baseline(S, W.softcore_3d(n=args.n, precision="c128"),
+                                                                 args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
