@@ -241,7 +241,7 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="points per axis")
     ap.add_argument("--profile-steps", type=int, default=10, help="steps of the per-launch event breakdown")
     ap.add_argument("--pass-reps", type=int, default=20, help="back-to-back launches per timed pass class")

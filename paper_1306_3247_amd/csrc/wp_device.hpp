@@ -420,4 +420,29 @@ __device__ __forceinline__ void store_from(T *p, cx<R> v) {
   *p = s;
 }
 
+// The same with the non-temporal hint (data streamed through once: no
+// point keeping it in the caches).
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+template <class R>
+__device__ __forceinline__ cx<R> load_nt_as(const float2 *p) {
+  const nt_f2 v = __builtin_nontemporal_load((const nt_f2 *)p);
+  return {(R)v.x, (R)v.y};
+}
+template <class R>
+__device__ __forceinline__ cx<R> load_nt_as(const double2 *p) {
+  const nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+  return {(R)v.x, (R)v.y};
+}
+template <class R>
+__device__ __forceinline__ void store_nt_from(float2 *p, cx<R> v) {
+  const nt_f2 s = {(float)v.x, (float)v.y};
+  __builtin_nontemporal_store(s, (nt_f2 *)p);
+}
+template <class R>
+__device__ __forceinline__ void store_nt_from(double2 *p, cx<R> v) {
+  const nt_d2 s = {(double)v.x, (double)v.y};
+  __builtin_nontemporal_store(s, (nt_d2 *)p);
+}
+
 }  // namespace wp

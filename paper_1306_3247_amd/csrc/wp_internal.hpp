@@ -20,6 +20,9 @@ enum : uint32_t {
   // next to its transforms, the pass along axis 1 the kinetic factor of bin
   // k1 + n1*k2.
   OP_SPLIT = 1u << 5,
+  // Cache hints for the pass's HBM reads / writes (results unchanged).
+  OP_LOAD_NT = 1u << 6,
+  OP_STORE_NT = 1u << 7,
 };
 
 struct GridDev {

@@ -146,7 +146,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
   const uint32_t ops = a.ops;
 
   cx<R> v[VPT];
-  if (valid) {
+  if (valid && (ops & OP_LOAD_NT)) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) v[u] = load_nt_as<R>(psi + base + ((int64_t)(t + L * u) << lgi));
+  } else if (valid) {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = load_as<R>(psi + base + ((int64_t)(t + L * u) << lgi));
   } else {
@@ -287,7 +290,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     if (ops & OP_FWD) line_fft<N, VPT, false>(v, t, tw, lds);  // starts with a barrier
   }
 
-  if (valid) {
+  if (valid && (ops & OP_STORE_NT)) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) store_nt_from(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
+  } else if (valid) {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) store_from(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
   }

@@ -170,3 +170,18 @@ def test_paul_trap_512_fp32_full_length(S, W):
     print(f"Paul trap 512^3 x 18500 FP32: max |<x> - classical| = {worst:.3e} m, norm drift {abs(o['norm'] - 1):.2e}")
     assert worst <= 1e-4 * 3.7e-8
     assert abs(o["norm"] - 1.0) <= 1e-5
+
+
+def test_softcore_512_slabs_and_cache_hints_bit_identical(S, W):
+    """At 512^3 the state is streamed with non-temporal hints, differently
+    for one slab and for several: the results are the same bits."""
+    prob = W.softcore_3d(n=512, steps=3, precision="c64")
+    prob.t0 = 9.0
+    out = []
+    for count in (1, 4, 16):
+        s = S.from_problem(prob)
+        s.set_slabs(count)
+        s.propagate(3)
+        out.append(s.get_state("c64"))
+        s.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])

@@ -163,6 +163,34 @@ def test_mixed_gaussian_physics(S, W, oracle_mod, precision):
         assert abs(o[k] - want[k]) <= tol * scale, (k, o[k], want[k])
 
 
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("n,v0", [(1000, "morse"), (2187, "softcore")])
+def test_1d_mixed_nonseparable(S, W, oracle_mod, n, v0, precision):
+    """Per-point potentials through the mixed-radix solver: the Morse
+    oscillator on 1000 = 2^3 5^3 points and a soft-core well on 3^7."""
+    prob = morse_dipole_1d(W, n, 40, precision)
+    if v0 == "softcore":
+        prob.grid.lo, prob.grid.hi = [-30.0], [30.0]
+        prob.pot.v0_kind, prob.pot.v0_par = "softcore", (1.0, 2.0, 0.0, 0.0)
+        prob.grid.mass = 1.0
+        prob.init = W.Gaussian([0.0], [1.0], [0.5])
+    got, ref, _ = run_both(S, oracle_mod, prob)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_paul_trap_mixed_grid(S, W, oracle_mod, precision):
+    """The Section 4.2 Paul trap (SI units) on a 60 x 48 x 45 grid at the
+    paper's spacing through the mixed-radix passes."""
+    prob = W.paul_trap_3d(n=64, steps=20, precision=precision, half_width=1.25e-7)
+    dx = 2.5e-7 / 64
+    prob.grid.n = [60, 48, 45]
+    prob.grid.lo = [-30 * dx, -24 * dx, -22.5 * dx]
+    prob.grid.hi = [30 * dx, 24 * dx, 22.5 * dx]
+    got, ref, _ = run_both(S, oracle_mod, prob)
+    assert rel_l2(got, ref) <= TOL[precision]
+
+
 def test_mixed_batch_rejected(S, W):
     p = W.modulated_trap_2d(n=4, steps=0, precision="c64")
     p.grid.n = [6, 10]
