@@ -8,8 +8,8 @@ arguments.  One bench step = one full time step of that grid (four line
 passes in the steady state).  The state is resident in HBM when timing starts.
 
 Prints one JSON line: site-steps/s of the FP32 path, the FP64 path beside it,
-the roofline of the dominant kernel (device time from HIP events around each
-launch), the FP32-vs-FP64 error of the run, and the CPU oracle timed on a
+the roofline of the dominant kernel (device time from HIP events attached to
+each of its launches inside real steps), the FP32-vs-FP64 error of the run, and the CPU oracle timed on a
 bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -237,6 +237,115 @@ def cpu_baseline(S, prob, budget_s: float):
     return base, parity
 
 
+def rocprof_summary(base: str, n: int) -> int:
+    """Summarise the four rocprofv3 runs of this benchmark (kernel trace,
+    SQ counters, FETCH_SIZE, WRITE_SIZE, written with -d base/<name> -o
+    <name> for name in trace, sq, fetch, write) as markdown on stdout, and
+    write base/traffic.json: HBM bytes per full-grid launch of every line-pass
+    kernel, each counter scaled by what it reads for the run's 1 GiB device
+    copy (--copy-calibration)."""
+    import collections
+    import re
+    import sqlite3
+
+    kinds = {"0": "F", "1": "V", "2": "K", "3": "VS", "4": "KS"}
+
+    def short(name):
+        m = re.match(r"void wp::(edge_)?pass_kernel<(\w+), (\w+), (\d+), (\w+), (\d), (\d)>", name)
+        if m:
+            lay = "strided" if m.group(5) == "true" else "contig"
+            head = "edge" if m.group(1) else "pass"
+            return f"{head}<{m.group(2)},{m.group(3)},{m.group(4)},{lay},{kinds[m.group(6)]},t{m.group(7)}>"
+        return name.split("(")[0].replace("void ", "")[:60]
+
+    def db(name):
+        return sqlite3.connect(os.path.join(base, name, f"{name}_results.db"))
+
+    # Launch order of the trace: runs of three or more consecutive launches
+    # of one kernel are back-to-back timing (variant tuning, isolated pass
+    # timing); shorter runs are launches inside steps (two in a row where the
+    # inverse middle pass of one x slab meets the forward pass of the next).
+    seq = [(short(nm), d) for nm, d in db("trace").execute("select name, duration from kernels order by start")]
+    dur = collections.defaultdict(list)
+    ctx = collections.defaultdict(lambda: {"step": [], "b2b": []})
+    full = {}
+    i = 0
+    while i < len(seq):
+        j = i
+        while j < len(seq) and seq[j][0] == seq[i][0]:
+            j += 1
+        k = seq[i][0]
+        for _, d in seq[i:j]:
+            dur[k].append(d)
+            ctx[k]["step" if j - i < 3 else "b2b"].append(d)
+        i = j
+    for nm, in db("trace").execute("select distinct name from kernels"):
+        full[short(nm)] = nm
+
+    def counters(name):
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        q = ("select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
+             "group by dispatch_id, counter_name")
+        for _, k, c, v in db(name).execute(q).fetchall():
+            per[short(k)][c].append(v)
+        return per
+
+    sq, fe, wr = counters("sq"), counters("fetch"), counters("write")
+    mean = lambda xs: sum(xs) / len(xs) if xs else float("nan")
+    copy = "__amd_rocclr_copyBuffer"
+    kib = (1 << 30) / 1024
+    sf = kib / max(fe[copy]["FETCH_SIZE"])
+    sw = kib / max(wr[copy]["WRITE_SIZE"])
+    print(f"Counter calibration (1 GiB device copy: 1 GiB read, 1 GiB written): FETCH_SIZE reads "
+          f"{max(fe[copy]['FETCH_SIZE']):.0f} KiB -> scale {sf:.4f}; WRITE_SIZE reads "
+          f"{max(wr[copy]['WRITE_SIZE']):.0f} KiB -> scale {sw:.4f}.")
+    print()
+    print("| kernel | launches | avg µs | in-step launches | in-step avg µs | back-to-back avg µs "
+          "| HBM read GB/launch | HBM write GB/launch | GB/s | LDS conflict cycles / LDS instr | VALU instr / wave |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    state = 8 * n ** 3
+    workload = f"softcore_3d_{n}"
+    classes = {"passV": ("axis0",), "edgeV": ("edge",), "passF": ("mid_fwd", "mid_inv"), "passK": ("last",)}
+    entries = {}
+    for k, ds in dur.items():
+        if "wp::" not in k and "pass<" not in k and "edge<" not in k:
+            continue
+        rd = [v * 1024 * sf for v in fe[k]["FETCH_SIZE"]]
+        wt = [v * 1024 * sw for v in wr[k]["WRITE_SIZE"]]
+        r, w = mean(rd) / 1e9, mean(wt) / 1e9
+        q = sq[k]
+        conf = mean(q["SQ_LDS_BANK_CONFLICT"]) / max(1.0, mean(q["SQ_INSTS_LDS"])) if q["SQ_INSTS_LDS"] else float("nan")
+        vpw = mean(q["SQ_INSTS_VALU"]) / max(1.0, mean(q["SQ_WAVES"])) if q["SQ_WAVES"] else float("nan")
+        c = ctx[k]
+        print(f"| `{k}` | {len(ds)} | {mean(ds) / 1e3:.1f} | {len(c['step'])} | "
+              f"{mean(c['step']) / 1e3:.1f} | {mean(c['b2b']) / 1e3:.1f} | {r:.3f} | {w:.3f} | "
+              f"{(r + w) / (mean(ds) * 1e-9):.0f} | {conf:.3f} | {vpw:.0f} |")
+        m = re.match(r"(pass|edge)<float,float,\d+,\w+,(\w+),t(\d)>", k)
+        cls = m and classes.get(m.group(1) + m.group(2))
+        if cls and len(rd) == len(wt):
+            # full-grid launches only (slab launches move a fraction of the state)
+            fl = [(a, b) for a, b in zip(rd, wt) if a >= 0.75 * state]
+            if fl:
+                e = {"kernel": full[k], "read_bytes": int(mean([a for a, _ in fl])),
+                     "write_bytes": int(mean([b for _, b in fl])), "launches": len(fl)}
+                e["bytes_per_launch"] = e["read_bytes"] + e["write_bytes"]
+                for cl in cls:
+                    entries[f"{workload}:{cl}:t{m.group(3)}"] = e
+    print()
+    print("Raw SQ counters (mean per dispatch):")
+    print()
+    print("```")
+    for k, q in sq.items():
+        if "pass<" in k or "edge<" in k or "wp::" in k:
+            print(k + ": " + ", ".join(f"{c}={mean(v):.4g}" for c, v in sorted(q.items())))
+    print("```")
+    with open(os.path.join(base, "traffic.json"), "w") as f:
+        json.dump({"kernel_hash": kernel_hash(), "source": "profiles/pass_kernels_softcore_3d_512_c64.md",
+                   "scale": {"FETCH_SIZE": round(sf, 4), "WRITE_SIZE": round(sw, 4)}, "entries": entries},
+                  f, indent=1)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,7 +374,11 @@ def main() -> int:
     ap.add_argument("--serve-budget-gib", type=float, default=192.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--rocprof-summary", metavar="DIR",
+                    help="summarise the rocprofv3 runs under DIR (no GPU work) and exit")
     args = ap.parse_args()
+    if args.rocprof_summary:
+        return rocprof_summary(args.rocprof_summary, args.n)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -332,33 +445,47 @@ def main() -> int:
             sx.close()
         s64.close()
 
-    # Roofline of the dominant kernel.  Every pass reads and writes the whole
-    # state once: 2 x state bytes per launch over the whole grid.  Each pass
-    # class is launched back to back on the handle's stream between one
-    # event pair (wp_time_pass), best of three rounds; the slowest class
-    # dominates a step.  An event pair around single launches inside a step
-    # (wp_profile_propagate, kept as passes_event_per_launch) delays each
-    # bracketed launch by up to ~0.1 ms, so it is not used for the roofline.
+    # Roofline of the dominant kernel, timed live inside real steps: every
+    # launch of `profile_steps` steps carries an event pair attached to its
+    # own dispatch (wp_profile_propagate), so the pair spans exactly that
+    # kernel and nothing is enqueued between kernels.  A first-axis pass
+    # covers the whole grid; a middle pass covers one x slab of it.  Each
+    # pass reads and writes its part of the state once: the algorithmic bytes
+    # of a launch are 2 x the bytes it covers.  The dominant class is the one
+    # with the most device time per step.  Each class is also launched back to
+    # back over the whole grid (wp_time_pass, best of three rounds), kept as
+    # passes_back_to_back.
     state_bytes = S.state_bytes(prob.grid, "c64")
     alg_bytes = 2 * state_bytes
+    nslab = s32.slabs()
+    prof = s32.profile_propagate(args.profile_steps)
+    share = {"axis0": 1, "edge": 1, "mid_fwd": nslab, "last": nslab, "mid_inv": nslab}
+    steady = {k: v for k, v in prof.items() if k in ("axis0", "mid_fwd", "last", "mid_inv")}
+    kind = max(steady, key=lambda k: steady[k][1])
+    count, total_ms = steady[kind]
+    avg_ms = total_ms / count
+    launch_bytes = alg_bytes // share[kind]
+    achieved = launch_bytes / (avg_ms / 1e3) / 1e9
     timed = {k: min(s32.time_pass(k, args.pass_reps) for _ in range(3)) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
-    kind, avg_ms = max(timed.items(), key=lambda kv: kv[1])
-    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     lg = int(np.log2(args.n))
     variant = {"axis0": S.tune_get(False, "c64", lg, True, "potential"),
                "mid_fwd": S.tune_get(False, "c64", lg, True, "fft"),
                "mid_inv": S.tune_get(False, "c64", lg, True, "fft"),
                "last": S.tune_get(False, "c64", lg, False, "kinetic")}
-    prof = s32.profile_propagate(args.profile_steps)
+    traffic = traffic_for(kind, workload, variant[kind]) if share[kind] == 1 else None
     out["roofline"] = {"bound": "hbm", "kernel": f"pass:{kind}", "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": traffic_for(kind, workload, variant[kind]), "variant": variant[kind],
-                       "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": alg_bytes, "reps": args.pass_reps,
-                       "slabs": s32.slabs(),
-                       "passes": {k: {"avg_ms": round(m, 4), "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)}
-                                  for k, m in timed.items()},
-                       "passes_event_per_launch": {k: {"launches": c, "avg_ms": round(m / c, 4)}
-                                                   for k, (c, m) in prof.items()}}
+                       "traffic": traffic, "variant": variant[kind], "avg_launch_ms": round(avg_ms, 4),
+                       "launches": count, "alg_bytes_per_launch": launch_bytes, "slabs": nslab,
+                       "timing": "in-step, dispatch-attached events",
+                       "passes_in_step": {k: {"launches": c, "avg_ms": round(m / c, 4),
+                                              "GB/s": round(alg_bytes / share.get(k, 1) / (m / c / 1e3) / 1e9, 1)
+                                              if k in share else None}
+                                          for k, (c, m) in prof.items()},
+                       "passes_back_to_back": {k: {"avg_ms": round(m, 4),
+                                                   "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)}
+                                               for k, m in timed.items()},
+                       "back_to_back_reps": args.pass_reps}
     # Whole-step view against the 4-pass byte model (64 B per site-step).
     step_gbs = 4 * alg_bytes * args.steps / (ms32 / 1e3) / 1e9
     out["step_roofline"] = {"model": "4 passes x (read+write) per step", "achieved": round(step_gbs, 1),

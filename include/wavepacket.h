@@ -245,14 +245,15 @@ enum {
 };
 
 /* Same work as wp_propagate(sim, nsteps) (the state advances identically),
- * with a HIP event pair around every kernel launch of the classes in
- * `kinds` (bit k for class k; 0xffffffff for all) on the handle's stream;
- * other launches run as in wp_propagate.  On return ms[k] holds the summed
- * device time (milliseconds) and count[k] the number of bracketed launches
- * of class k, for k < WP_PASS_KINDS (arrays of at least WP_PASS_KINDS
- * entries, caller-owned).  Synchronises.  Meant for measurement: each event
- * pair adds a small delay to its launch.  nsteps must be in 1..100000
- * (WP_EINVAL otherwise). */
+ * timing every kernel launch of the classes in `kinds` (bit k for class k;
+ * 0xffffffff for all) with a HIP event pair attached to that dispatch
+ * (hipExtLaunchKernel: the events take the kernel's own start and end
+ * times, and nothing is enqueued between kernels); other launches run as in
+ * wp_propagate.  On return ms[k] holds the summed device time
+ * (milliseconds) and count[k] the number of timed launches of class k, for
+ * k < WP_PASS_KINDS (arrays of at least WP_PASS_KINDS entries,
+ * caller-owned).  Synchronises.  nsteps must be in 1..100000 (WP_EINVAL
+ * otherwise). */
 wp_status wp_profile_propagate(wp_sim *sim, uint64_t nsteps, uint32_t kinds, double *ms, uint64_t *count);
 
 /* Device time of one line-pass class of a 2D/3D (or split 1D) step: the

@@ -674,6 +674,10 @@ namespace {
 
 // Walk the launch sequence of `nsteps` steps, calling launch(kind, fn) for
 // each kernel, where fn() enqueues it.  Kinds are the WP_PASS_* values.
+// Events that only time device work: no system-scope fence at record time,
+// so that no cache write-back or invalidation lands inside the timed interval.
+inline hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 template <class Launch>
 hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
   const double tau_half = 0.5 * s->g.dt / s->g.hbar;
@@ -811,23 +815,29 @@ wp_status wp_profile_propagate(wp_sim *s, uint64_t nsteps, uint32_t kinds, doubl
     ms[k] = 0.0;
     count[k] = 0;
   }
-  // One event pair per launch; durations are read after the whole sequence
-  // so that the host never waits between launches.
+  // One event pair per launch, attached to the dispatch itself, so that the
+  // pair spans exactly that kernel and nothing is enqueued between kernels;
+  // durations are read after the whole sequence, so that the host never
+  // waits between launches.
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
   hipError_t e = run_schedule(s, nsteps, [&](int kind, auto &&fn) {
     if (!((kinds >> kind) & 1u)) return fn();
     hipEvent_t a, b;
-    hipError_t r = hipEventCreate(&a);
+    hipError_t r = timing_event(&a);
     if (r != hipSuccess) return r;
-    r = hipEventCreate(&b);
+    r = timing_event(&b);
     if (r != hipSuccess) {
       (void)hipEventDestroy(a);
       return r;
     }
     ev.push_back({kind, {a, b}});
-    r = hipEventRecord(a, s->stream);
-    if (r == hipSuccess) r = fn();
-    if (r == hipSuccess) r = hipEventRecord(b, s->stream);
+    wp::DispatchEvents &d = wp::tl_dispatch_events;
+    d = {a, b, false};
+    r = fn();
+    const bool used = d.used;
+    d = {};
+    // every launcher of the schedule attaches the events
+    if (r == hipSuccess && !used) r = hipErrorNotSupported;
     return r;
   });
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -851,8 +861,8 @@ wp_status wp_profile_propagate(wp_sim *s, uint64_t nsteps, uint32_t kinds, doubl
 // warm-up launch), between one event pair on the handle's stream.
 static hipError_t time_launches(wp_sim *s, const wp::PassArgs &a, uint32_t reps, double *ms) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
+  hipError_t e = timing_event(&e0);
+  if (e == hipSuccess) e = timing_event(&e1);
   if (e == hipSuccess) e = launch_any(s, a, s->stream);
   if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
   for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_any(s, a, s->stream);
@@ -970,8 +980,8 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
     double best_ms = 0.0;
     bool first = true;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    e = timing_event(&e0);
+    if (e == hipSuccess) e = timing_event(&e1);
     const int top = s->lg[0] < WP_TUNE_SLAB_CHOICES - 1 ? s->lg[0] : WP_TUNE_SLAB_CHOICES - 1;
     const uint64_t steps = 1 + reps / 4;
     double sbest[WP_TUNE_SLAB_CHOICES] = {};
@@ -1576,8 +1586,8 @@ wp_status wp_batch_autotune(wp_batch *b, uint32_t reps) {
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   b->step_pending = false;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (e == hipSuccess) e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = timing_event(&e0);
+  if (e == hipSuccess) e = timing_event(&e1);
   for (const GroupSpec &sp : b->specs) {
     if (e != hipSuccess) break;
     const int var = sp.slot == SLOT_V ? V_STEADY : sp.slot == SLOT_K ? K_LAST : sp.slot == SLOT_FFWD ? F_FWD : F_INV;

@@ -300,22 +300,19 @@ hipError_t launch_gpass(int prec, const GPassArgs &ga, hipStream_t s) {
   const int kind = (ops & OP_V) ? PK_V : (ops & OP_K) ? PK_K : PK_F;
   const dim3 g((unsigned)blocks), b(kGThreads);
   if (prec == 2) {
-    if (kind == PK_V) hipLaunchKernelGGL((gpass_kernel<double, PK_V>), g, b, 0, s, ga);
-    else if (kind == PK_K) hipLaunchKernelGGL((gpass_kernel<double, PK_K>), g, b, 0, s, ga);
-    else hipLaunchKernelGGL((gpass_kernel<double, PK_F>), g, b, 0, s, ga);
-  } else {
-    if (kind == PK_V) hipLaunchKernelGGL((gpass_kernel<float, PK_V>), g, b, 0, s, ga);
-    else if (kind == PK_K) hipLaunchKernelGGL((gpass_kernel<float, PK_K>), g, b, 0, s, ga);
-    else hipLaunchKernelGGL((gpass_kernel<float, PK_F>), g, b, 0, s, ga);
+    if (kind == PK_V) return launch_kernel(gpass_kernel<double, PK_V>, g, b, s, ga);
+    if (kind == PK_K) return launch_kernel(gpass_kernel<double, PK_K>, g, b, s, ga);
+    return launch_kernel(gpass_kernel<double, PK_F>, g, b, s, ga);
   }
-  return hipGetLastError();
+  if (kind == PK_V) return launch_kernel(gpass_kernel<float, PK_V>, g, b, s, ga);
+  if (kind == PK_K) return launch_kernel(gpass_kernel<float, PK_K>, g, b, s, ga);
+  return launch_kernel(gpass_kernel<float, PK_F>, g, b, s, ga);
 }
 
 hipError_t launch_gsolve1d(int prec, const Solve1DArgs &a, const GPlan &plan, hipStream_t s) {
   if (a.g.n[0] < 2 || a.g.n[0] > kMaxMixed || plan.nst < 1 || plan.nst > kMaxStages) return hipErrorInvalidValue;
-  if (prec == 2) hipLaunchKernelGGL(gsolve1d_kernel<double>, dim3(1), dim3(kGThreads), 0, s, a, plan);
-  else hipLaunchKernelGGL(gsolve1d_kernel<float>, dim3(1), dim3(kGThreads), 0, s, a, plan);
-  return hipGetLastError();
+  if (prec == 2) return launch_kernel(gsolve1d_kernel<double>, dim3(1), dim3(kGThreads), s, a, plan);
+  return launch_kernel(gsolve1d_kernel<float>, dim3(1), dim3(kGThreads), s, a, plan);
 }
 
 }  // namespace wp

@@ -1,6 +1,7 @@
 // wp_internal.hpp -- kernel argument blocks and launcher entry points shared
 // by the kernel translation unit and the C ABI.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -151,6 +152,29 @@ struct GPassArgs {
   int64_t inner;  // product of the lengths after the line axis
   GPlan plan;     // of the line axis; p.tw holds its stage twiddles
 };
+
+// Events to attach to the next kernel dispatch of this host thread.  When
+// `start` is set, the launchers of a single-handle schedule (line passes,
+// mixed-radix passes, 1D solves, waveform coefficients) launch through
+// hipExtLaunchKernel, so that the two events take the start and end times of
+// that dispatch itself, with no marker between kernels, and set `used`.
+struct DispatchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool used = false;
+};
+inline thread_local DispatchEvents tl_dispatch_events;
+
+template <class K, class... A>
+inline hipError_t launch_kernel(K kernel, dim3 grid, dim3 block, hipStream_t s, A... args) {
+  DispatchEvents &d = tl_dispatch_events;
+  if (d.start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, d.start, d.stop, 0, args...);
+    d.used = true;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
+  return hipGetLastError();
+}
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s);

@@ -179,7 +179,7 @@ static hipError_t launch_solve1d_t(const Solve1DArgs &a, hipStream_t s, const So
   if (batch)
     hipLaunchKernelGGL((solve1d_batch_kernel<S, R, N>), dim3(count), dim3(fft_shape<N>::L), 0, s, batch, a.nsteps);
   else
-    hipLaunchKernelGGL((solve1d_kernel<S, R, N>), dim3(1), dim3(fft_shape<N>::L), 0, s, a);
+    return launch_kernel(solve1d_kernel<S, R, N>, dim3(1), dim3(fft_shape<N>::L), s, a);
   return hipGetLastError();
 }
 
@@ -243,8 +243,7 @@ __global__ void coef_kernel(PotDev p, TimeDev T, int count, double *out) {
 
 hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, double *out, hipStream_t s) {
   const int n = count * CO_COUNT;
-  hipLaunchKernelGGL(coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, T, count, out);
-  return hipGetLastError();
+  return launch_kernel(coef_kernel, dim3((n + 255) / 256), dim3(256), s, p, T, count, out);
 }
 
 // Many solves at once; the step of solve i is read from step_dev[i] on the

@@ -274,17 +274,36 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
       const int kind = a.pot.v0_kind;
       const double p0 = a.pot.v0_par[0], p1 = a.pot.v0_par[1], p2 = a.pot.v0_par[2];
       const double r2off = rho2 + p1;
+      // Soft core: on this line q = x^2 + r2off lies between r2off and
+      // xm^2 + r2off (xm the largest |x|), so one check of the ends admits
+      // the FP32-range reciprocal square root for every point, and
+      // |th| <= |th_line| + |ca| xm + |cb| xm^2 + |cs p0| / sqrt(r2off)
+      // admits the short series for every point; other lines choose point
+      // by point.
+      const double xm = fmax(fabs(lo), fabs(lo + (double)(N - 1) * dx));
+      const bool soft_fast =
+          kind == 1 && __all(r2off > 1e-30 && fma(xm, xm, r2off) < 1e30 &&
+                             fabs(th_line) + xm * (fabs(ca) + xm * fabs(cb)) + fabs(cs * p0) * rsqrt(r2off) <= 0.0625);
+      if (soft_fast) {
 #pragma unroll
-      for (int u = 0; u < VPT; ++u) {
-        const double x = lo + (double)(t + L * u) * dx;
-        double th = th_line + x * fma(cb, x, ca);
-        if (kind == 1) {
-          th -= cs * p0 * rsqrt_fast(fma(x, x, r2off));
-        } else {
-          const double e = 1.0 - exp(-p1 * (x - p2));
-          th += cs * p0 * e * e;
+        for (int u = 0; u < VPT; ++u) {
+          const double x = lo + (double)(t + L * u) * dx;
+          const double th = th_line + x * fma(cb, x, ca) - cs * p0 * rsqrt_newton(fma(x, x, r2off));
+          v[u] = mul_acc(v[u], expmi_tiny(th));
         }
-        v[u] = mul_acc(v[u], expmi_wave(th));
+      } else {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+          const double x = lo + (double)(t + L * u) * dx;
+          double th = th_line + x * fma(cb, x, ca);
+          if (kind == 1) {
+            th -= cs * p0 * rsqrt_fast(fma(x, x, r2off));
+          } else {
+            const double e = 1.0 - exp(-p1 * (x - p2));
+            th += cs * p0 * e * e;
+          }
+          v[u] = mul_acc(v[u], expmi_wave(th));
+        }
       }
     }
     if (ops & OP_FWD) line_fft<N, VPT, false>(v, t, tw, lds);  // starts with a barrier
@@ -303,6 +322,18 @@ template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
 __global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND, TUNE>::THREADS),
                                   (pass_cfg<S, R, N, STRIDED, KIND, TUNE>::WAVES_EU))
     pass_kernel(PassArgs a) {
+  using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
+  const unsigned blk = C::PAIR ? pair_blocks(blockIdx.x, gridDim.x) : blockIdx.x;
+  pass_body<S, R, N, STRIDED, KIND, TUNE>(a, a.coef, blk);
+}
+
+// The same first-axis potential pass under its own symbol, for the passes
+// that open or close a propagation (one transform instead of two), so that
+// per-kernel profiles report them apart from the steady-state pass.
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
+__global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND, TUNE>::THREADS),
+                                  (pass_cfg<S, R, N, STRIDED, KIND, TUNE>::WAVES_EU))
+    edge_pass_kernel(PassArgs a) {
   using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
   const unsigned blk = C::PAIR ? pair_blocks(blockIdx.x, gridDim.x) : blockIdx.x;
   pass_body<S, R, N, STRIDED, KIND, TUNE>(a, a.coef, blk);
@@ -334,8 +365,12 @@ template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
 hipError_t launch_pass_t(const PassArgs &a, hipStream_t s) {
   using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
   const int64_t blocks = (a.n_lines + C::TILE - 1) / C::TILE;
-  hipLaunchKernelGGL((pass_kernel<S, R, N, STRIDED, KIND, TUNE>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
-  return hipGetLastError();
+  if constexpr (KIND == PK_V && STRIDED) {
+    if (!((a.ops & OP_PRE_INV) && (a.ops & OP_FWD)))
+      return launch_kernel(edge_pass_kernel<S, R, N, STRIDED, KIND, TUNE>, dim3((unsigned)blocks), dim3(C::THREADS),
+                           s, a);
+  }
+  return launch_kernel(pass_kernel<S, R, N, STRIDED, KIND, TUNE>, dim3((unsigned)blocks), dim3(C::THREADS), s, a);
 }
 
 // What one launch needs: kind (PK_*), layout, tuning variant.  The kind of a

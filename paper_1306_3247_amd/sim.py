@@ -319,9 +319,9 @@ class Simulation:
     PASS_KINDS = ("solve1d", "axis0", "mid_fwd", "last", "mid_inv", "edge", "coef")
 
     def profile_propagate(self, nsteps: int, kinds=None) -> dict:
-        """Propagate with a device-timed event pair around every kernel of
-        the given classes (names from PASS_KINDS; all by default); returns
-        {kind: (launches, total_ms)} for the bracketed kinds that ran."""
+        """Propagate with an event pair attached to the dispatch of every
+        kernel of the given classes (names from PASS_KINDS; all by default);
+        returns {kind: (launches, total_ms)} for the timed kinds that ran."""
         mask = 0xFFFFFFFF if kinds is None else sum(1 << self.PASS_KINDS.index(k) for k in kinds)
         ms = (C.c_double * 8)()
         cnt = (C.c_uint64 * 8)()
