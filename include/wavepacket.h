@@ -280,14 +280,16 @@ wp_status wp_time_pass(wp_sim *sim, int32_t kind, uint32_t reps, double *ms);
 #define WP_TUNE_VARIANTS 4
 #define WP_TUNE_SLAB_CHOICES 8
 
-/* Time every variant of the handle's line passes ([0] potential pass of the
- * first axis, [1] middle-axis FFT (3D), [2] kinetic pass of the last axis)
- * over `reps` back-to-back launches each, on a device copy of the state
- * (the state itself is unchanged; one state-sized scratch buffer is
- * allocated on first use), and store the fastest in the table; on 3D
- * power-of-two grids then time whole steps with 1, 2, 4, ... x slabs (see
- * wp_set_slabs) and keep the fastest count for this handle.  ms, if not
- * NULL, receives 3 x WP_TUNE_VARIANTS average milliseconds per launch
+/* Tune the handle's line passes ([0] potential pass of the first axis, [1]
+ * middle-axis FFT (3D), [2] kinetic pass of the last axis) on a device copy
+ * of the state (the state itself is unchanged; one state-sized scratch
+ * buffer is allocated on first use): first every variant of each class over
+ * `reps` back-to-back launches on the whole grid, the fastest stored in the
+ * table; on 3D power-of-two grids then whole steps with 1, 2, 4, ... x slabs
+ * (see wp_set_slabs), the fastest count kept for this handle; last, for each
+ * class in turn, whole steps with each of its variants (the others at their
+ * chosen ones), the fastest stored.  ms, if not NULL, receives 3 x
+ * WP_TUNE_VARIANTS milliseconds per step of that last round (class-major)
  * followed by WP_TUNE_SLAB_CHOICES milliseconds per step for 2^0 .. 2^7
  * slabs (NaN where not tried).  Passes built afterwards by any handle use
  * the table; a 1D grid solved in one workgroup and mixed-length grids have

@@ -939,6 +939,9 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
     int axis;
     uint32_t ops;
   } cls[3] = {{0, wp::OP_PRE_INV | wp::OP_V | wp::OP_FWD}, {1, wp::OP_FWD}, {last, wp::OP_FWD | wp::OP_K | wp::OP_POST_INV}};
+  // Table key and candidates of each class.
+  int ckind[3] = {}, clg[3] = {}, cnc[3] = {}, ccand[3][4] = {};
+  bool cstrided[3] = {};
   for (int c = 0; c < 3 && e == hipSuccess; ++c) {
     if (c == 1 && s->vdim != 3) continue;
     wp::PassArgs a = pass_args(s, cls[c].axis, cls[c].ops);
@@ -947,8 +950,12 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
     if (a.ops & wp::OP_V) e = current_coef(s, a);
     const int kind = kind_of(s, cls[c].axis, cls[c].ops);
     const int lgN = s->vlg[cls[c].axis];
-    int cand[4];
+    int *cand = ccand[c];
     const int nc = wp::tune_candidates(s->prec, lgN, kind, cand);
+    ckind[c] = kind;
+    clg[c] = lgN;
+    cnc[c] = nc;
+    cstrided[c] = a.lg_inner > 0;
     // Two rounds over the candidates, the best of each kept: the first
     // launches after an idle spell run slower than later ones.
     double tbest[4] = {0, 0, 0, 0};
@@ -962,7 +969,6 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
     int best = 0;
     double best_ms = 0.0;
     for (int i = 0; i < nc && e == hipSuccess; ++i) {
-      if (ms) ms[c * wp::kTuneSlots + cand[i]] = tbest[i];
       if (i == 0 || tbest[i] < best_ms) {
         best = cand[i];
         best_ms = tbest[i];
@@ -1011,6 +1017,51 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
     if (e1) (void)hipEventDestroy(e1);
     s->psi = keep;
     s->slab_lg = e == hipSuccess ? best : keep_lg;
+  }
+  // Whole steps per variant: each class in turn runs every candidate inside
+  // real steps (the chosen slab count, the other classes at their chosen
+  // variants) and keeps the fastest.  Launches over the whole grid, timed
+  // above, only give the starting point: the slab launches and cache hints
+  // of a step differ from them.
+  if (e == hipSuccess) {
+    void *keep = s->psi;
+    s->psi = s->scratch;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = timing_event(&e0);
+    if (e == hipSuccess) e = timing_event(&e1);
+    const uint64_t steps = 2 + reps / 2;
+    auto direct = [](int, auto &&fn) { return fn(); };
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+      if (c == 1 && s->vdim != 3) continue;
+      const int nc = cnc[c];
+      double tbest[4] = {0, 0, 0, 0};
+      for (int round = 0; round < 2 && e == hipSuccess; ++round)
+        for (int i = 0; i < nc && e == hipSuccess; ++i) {
+          tune_store(0, s->prec, clg[c], cstrided[c], ckind[c], ccand[c][i]);
+          e = run_schedule(s, 1, direct);  // warm-up
+          if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+          if (e == hipSuccess) e = run_schedule(s, steps, direct);
+          if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float m = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
+          const double per = (double)m / (double)steps;
+          if (e == hipSuccess && (round == 0 || per < tbest[i])) tbest[i] = per;
+        }
+      int best = ccand[c][0];
+      double best_ms = 0.0;
+      for (int i = 0; i < nc && e == hipSuccess; ++i) {
+        if (ms) ms[c * wp::kTuneSlots + ccand[c][i]] = tbest[i];
+        if (i == 0 || tbest[i] < best_ms) {
+          best = ccand[c][i];
+          best_ms = tbest[i];
+        }
+      }
+      if (e == hipSuccess) tune_store(0, s->prec, clg[c], cstrided[c], ckind[c], best);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    s->psi = keep;
   }
   if (e != hipSuccess) return hip_fail(s, e, "autotune");
   s->err.clear();

@@ -139,19 +139,23 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
   const int t = STRIDED ? tid / TILE : tid % L;
   const int64_t line = (int64_t)blk * TILE + tau;
   const bool valid = line < a.n_lines;
-  const int lgi = a.lg_inner;
+  // Contiguous lines are those of the last axis (nothing inside them).
+  const int lgi = STRIDED ? a.lg_inner : 0;
   const int64_t o = line >> lgi, c = line & (((int64_t)1 << lgi) - 1);
   const int64_t base = (o << (fft_shape<N>::lg + lgi)) + c;
-  T *psi = (T *)a.psi;
+  // Element t + L*u of this thread's line is at pt + u*ustep (ustep is the
+  // same for the whole workgroup).
+  T *const pt = (T *)a.psi + base + ((int64_t)t << lgi);
+  const int64_t ustep = (int64_t)L << lgi;
   const uint32_t ops = a.ops;
 
   cx<R> v[VPT];
   if (valid && (ops & OP_LOAD_NT)) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = load_nt_as<R>(psi + base + ((int64_t)(t + L * u) << lgi));
+    for (int u = 0; u < VPT; ++u) v[u] = load_nt_as<R>(pt + u * ustep);
   } else if (valid) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = load_as<R>(psi + base + ((int64_t)(t + L * u) << lgi));
+    for (int u = 0; u < VPT; ++u) v[u] = load_as<R>(pt + u * ustep);
   } else {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
@@ -311,10 +315,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
 
   if (valid && (ops & OP_STORE_NT)) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) store_nt_from(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
+    for (int u = 0; u < VPT; ++u) store_nt_from(pt + u * ustep, v[u]);
   } else if (valid) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) store_from(psi + base + ((int64_t)(t + L * u) << lgi), v[u]);
+    for (int u = 0; u < VPT; ++u) store_from(pt + u * ustep, v[u]);
   }
 }
 

@@ -339,8 +339,10 @@ class Simulation:
     TUNE_CLASSES = ("axis0", "mid", "last")
 
     def autotune(self, reps: int = 10) -> dict:
-        """Time every kernel variant of this grid's line passes and store the
-        fastest in the tuning table; returns {class: {variant: ms}}."""
+        """Tune this grid's line passes (see wp_autotune): the fastest
+        variant of each class goes to the tuning table and the fastest slab
+        count to this handle.  Returns {class: {variant: ms per step}} and
+        "slabs": {count: ms per step} for what was timed."""
         ms = (C.c_double * (3 * TUNE_VARIANTS + TUNE_SLAB_CHOICES))()
         self._check(lib.wp_autotune(self._h, int(reps), ms), "wp_autotune")
         out = {}
