@@ -193,18 +193,33 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const cx<doubl
   }
 }
 
-template <int N, int VPT, int RAD, int LS, bool INV, class R, class Lds>
+// Ordering of an LDS exchange.  WAVE: every line is held by the threads of
+// one wavefront and stored in its own part of LDS, so only that wavefront
+// takes part; its LDS operations are performed in program order, and the
+// wavefront-scope fence keeps the compiler from moving LDS accesses across.
+// Otherwise the whole workgroup meets at a barrier.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int N, int VPT, int RAD, int LS, bool INV, bool WAVE, class R, class Lds>
 __device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
   constexpr int L = N / VPT;
   fft_stage<N, VPT, RAD, LS, INV>(v, t, tw, lds);
   if constexpr (LS * RAD < N) {
-    __syncthreads();
+    lds_sync<WAVE>();
     const int pt = pad16(t);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = lds(pt + L * u + ((L * u) >> 4));
     // The next stage writes LDS only if it is not the last one.
-    if constexpr (LS * RAD * 8 < N) __syncthreads();
-    fft_stages<N, VPT, 8, LS * RAD, INV>(v, t, tw, lds);
+    if constexpr (LS * RAD * 8 < N) lds_sync<WAVE>();
+    fft_stages<N, VPT, 8, LS * RAD, INV, WAVE>(v, t, tw, lds);
   }
 }
 
@@ -212,11 +227,13 @@ __device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const cx<doub
 // contains barriers) whether or not its line is valid.  It starts with a
 // barrier so that earlier LDS reads of the same buffer are complete.
 // `Lds` maps a padded position (see pad16) of this thread's line to an LDS
-// reference.
-template <int N, int VPT, bool INV, class R, class Lds>
+// reference.  WAVE (see lds_sync): each line lies within one wavefront, and
+// the caller has already synchronised the workgroup after any LDS it fills
+// together (twiddles, tables).
+template <int N, int VPT, bool INV, bool WAVE = false, class R, class Lds>
 __device__ __forceinline__ void line_fft(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
-  if constexpr (N > 8) __syncthreads();
-  fft_stages<N, VPT, fft_shape<N, VPT>::R0, 1, INV>(v, t, tw, lds);
+  if constexpr (N > 8) lds_sync<WAVE>();
+  fft_stages<N, VPT, fft_shape<N, VPT>::R0, 1, INV, WAVE>(v, t, tw, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -238,10 +238,13 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     cx<double> kl = {1.0, 0.0};
     for (int d = 0; d < a.g.ndim; ++d)
       if (d != a.axis) kl = cmul(kl, a.ktab[d][idx[d]]);
-    line_fft<N, VPT, false>(v, t, tw, lds);
+    // Last-axis lines of at most 64 threads lie within one wavefront each;
+    // the tables were shared after the barrier above.
+    constexpr bool WAVE = !STRIDED && L <= 64;
+    line_fft<N, VPT, false, WAVE>(v, t, tw, lds);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_ktab[t + L * u], kl));
-    line_fft<N, VPT, true>(v, t, tw, lds);
+    line_fft<N, VPT, true, WAVE>(v, t, tw, lds);
   } else {
     const double *s_coef = coef;  // uniform: scalar loads
     const int ax = a.axis;
