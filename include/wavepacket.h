@@ -299,12 +299,17 @@ wp_status wp_autotune(wp_sim *sim, uint32_t reps, double *ms);
 
 /* 3D power-of-two grids: run the middle passes of a step (forward FFT of
  * the middle axis, kinetic pass of the last axis, inverse FFT of the
- * middle axis) on `count` slabs of consecutive x planes, one slab after the
- * other, so that a slab stays in the GPU's memory-side cache between its
- * three passes and only the first pass reads it from HBM.  The arithmetic
- * is the same (results are bit-identical for every count).  count: a power
- * of two up to n0; 1 for other grids.  The default keeps slabs at most
- * 256 MiB.  WP_EINVAL otherwise. */
+ * middle axis) on `count` slabs of consecutive x planes, so that a slab
+ * stays in the GPU's memory-side cache between its three passes and only
+ * the first pass reads it from HBM.  With more than one slab, even slabs
+ * run on the handle's stream and odd ones on a second stream the library
+ * creates for the handle (default priority), forked from and joined back
+ * to the handle's stream by events around the middle of every step, so
+ * that work queued on the handle's stream still sees the whole step.  The
+ * arithmetic is the same (results are bit-identical for every count).
+ * count: a power of two up to n0; 1 for other grids.  The default keeps
+ * slabs at most 128 MiB (two in flight fit the cache).  WP_EINVAL
+ * otherwise. */
 wp_status wp_set_slabs(wp_sim *sim, uint32_t count);
 /* The handle's slab count (0 for a NULL handle). */
 uint32_t wp_get_slabs(const wp_sim *sim);

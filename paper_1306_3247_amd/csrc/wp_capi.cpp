@@ -31,10 +31,15 @@ struct wp_sim {
   bool mixed = false;
   wp::GPlan plan[3] = {};
   // 3D power-of-two grids: the middle passes of a step (y forward, z
-  // kinetic, y inverse) run on 2^slab_lg slabs of consecutive x planes one
-  // slab at a time, so that a slab stays in the memory-side cache between
-  // the three passes.
+  // kinetic, y inverse) run on 2^slab_lg slabs of consecutive x planes, so
+  // that a slab stays in the memory-side cache between the three passes.
+  // Even slabs run on `stream`, odd ones on `side` (created on first use),
+  // forked after the first-axis pass and joined before the next one by the
+  // two events, so that one slab's passes fill the gaps and tails of the
+  // other's.
   int slab_lg = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int vdim = 1;
   int vlg[3] = {0, 0, 0};
   int64_t total = 0;
@@ -276,6 +281,20 @@ void release(wp_sim *s) {
   if (s->d_gauss) (void)hipFree(s->d_gauss);
   if (s->ev_gauss) (void)hipEventDestroy(s->ev_gauss);
   if (s->d_wsplit) (void)hipFree(s->d_wsplit);
+  if (s->side) (void)hipStreamDestroy(s->side);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+}
+
+// The second stream of the slab schedule and its fork/join events (default
+// priority, like every stream of the library).
+hipError_t ensure_side(wp_sim *s) {
+  if (s->side) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+  if (e != hipSuccess) s->side = nullptr;
+  return e;
 }
 
 // Precision of the stored state (WP_C64X keeps an FP32 state).
@@ -376,9 +395,10 @@ wp::PassArgs slab_args(const wp_sim *s, wp::PassArgs a, int slab) {
 // streamed through each pass once, so its reads and writes bypass the
 // caches (non-temporal), except where a slab is read again by the next
 // pass of its group (see slab_args): the group's first pass reads
-// non-temporally and keeps its writes, the last keeps its reads and writes
-// non-temporally.  (Measured on MI355X at 512^3: 1-3 % faster steps in
-// FP32, 3-4 % slower in FP64, where the hints are therefore not used.)
+// non-temporally and keeps its writes, the later ones keep their reads and
+// writes.  (Measured on MI355X at 512^3: 1-3 % faster steps in FP32, 3-4 %
+// slower in FP64, where the hints are therefore not used; with slabs,
+// non-temporal writes in the group's last pass cost 0.7 % of a step.)
 constexpr uint64_t kCacheBytes = (uint64_t)256 << 20;
 bool streams_state(const wp_sim *s) {
   return s->psi_bytes > kCacheBytes && !s->mixed && storage_prec(s) == WP_C64;
@@ -387,10 +407,12 @@ constexpr uint32_t kNT = wp::OP_LOAD_NT | wp::OP_STORE_NT;
 
 // Default slab count: slabs of at most 256 MiB (the size the autotuner
 // picks on MI355X for 512^3 in FP32 and FP64).
+// Default slab count: two slabs in flight (one per stream) fit the 256 MB
+// memory-side cache.
 int default_slab_lg(const wp_sim *s) {
   if (s->vdim != 3 || s->mixed || s->split) return 0;
   int lg = 0;
-  while ((s->psi_bytes >> lg) > ((uint64_t)256 << 20) && lg < s->lg[0]) ++lg;
+  while ((s->psi_bytes >> lg) > ((uint64_t)128 << 20) && lg < s->lg[0]) ++lg;
   return lg;
 }
 
@@ -684,8 +706,8 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
   const double tau_full = s->g.dt / s->g.hbar;
   const int prec = s->prec;
   hipStream_t st = s->stream;
-  auto pass = [&](int kind, const wp::PassArgs &a) {
-    return launch(kind, [&]() { return launch_any(s, a, st); });
+  auto pass = [&](int kind, const wp::PassArgs &a, hipStream_t q) {
+    return launch(kind, [&]() { return launch_any(s, a, q); });
   };
   // The potential's waveform values come from a table filled for up to
   // kCoefChunk consecutive step times at once; the stream orders each refill
@@ -739,19 +761,32 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
   const uint32_t nt_v = stream ? kNT : 0u;                                          // first-axis passes
   const uint32_t nt_first = stream ? (s->slab_lg ? wp::OP_LOAD_NT : kNT) : 0u;      // first middle pass
   const uint32_t nt_mid = stream && s->slab_lg == 0 ? kNT : 0u;                     // the kinetic pass of 3D
-  const uint32_t nt_last = stream ? (s->slab_lg ? wp::OP_STORE_NT : kNT) : 0u;      // last middle pass
+  const uint32_t nt_last = stream && s->slab_lg == 0 ? kNT : 0u;                    // last middle pass
+  // Slabs alternate between the handle's stream and the second one.
+  const int nslab = 1 << s->slab_lg;
+  if (nslab > 1) {
+    if (hipError_t r = ensure_side(s); r != hipSuccess) return r;
+  }
   auto middle = [&](bool half_k) -> hipError_t {
     hipError_t r = hipSuccess;
-    const int nslab = 1 << s->slab_lg;
+    if (nslab > 1) {
+      r = hipEventRecord(s->ev_fork, st);
+      if (r == hipSuccess) r = hipStreamWaitEvent(s->side, s->ev_fork, 0);
+    }
     for (int sl = 0; sl < nslab && r == hipSuccess; ++sl) {
+      const hipStream_t q = (sl & 1) ? s->side : st;
       for (int d = 1; d < last && r == hipSuccess; ++d)
-        r = pass(WP_PASS_MID_FWD, slab_args(s, pass_args(s, d, wp::OP_FWD | nt_first), sl));
+        r = pass(WP_PASS_MID_FWD, slab_args(s, pass_args(s, d, wp::OP_FWD | nt_first), sl), q);
       if (r != hipSuccess) return r;
       wp::PassArgs k = pass_args(s, last, wp::OP_FWD | wp::OP_K | wp::OP_POST_INV | (last == 1 ? kNT & nt_v : nt_mid));
       if (half_k) use_half_kinetic(s, k);
-      r = pass(WP_PASS_LAST, slab_args(s, k, sl));
+      r = pass(WP_PASS_LAST, slab_args(s, k, sl), q);
       for (int d = last - 1; d >= 1 && r == hipSuccess; --d)
-        r = pass(WP_PASS_MID_INV, slab_args(s, pass_args(s, d, wp::OP_PRE_INV | nt_last), sl));
+        r = pass(WP_PASS_MID_INV, slab_args(s, pass_args(s, d, wp::OP_PRE_INV | nt_last), sl), q);
+    }
+    if (nslab > 1 && r == hipSuccess) {
+      r = hipEventRecord(s->ev_join, s->side);
+      if (r == hipSuccess) r = hipStreamWaitEvent(st, s->ev_join, 0);
     }
     return r;
   };
@@ -762,7 +797,7 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
     wp::PassArgs a0 = pass_args(s, 0, wp::OP_V | wp::OP_FWD | nt_v);
     e = coef_at((int64_t)s->step, 0.0, &a0.coef);
     a0.vtau = tau_half;
-    if (e == hipSuccess) e = pass(WP_PASS_EDGE, a0);
+    if (e == hipSuccess) e = pass(WP_PASS_EDGE, a0, st);
     for (uint64_t j = 0; j < nsteps && e == hipSuccess; ++j) {
       e = middle(false);
       if (e != hipSuccess) break;
@@ -770,20 +805,20 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
       wp::PassArgs a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | (lastj ? 0u : wp::OP_FWD) | nt_v);
       e = coef_at((int64_t)(s->step + j + 1), 0.0, &a.coef);
       a.vtau = lastj ? tau_half : tau_full;
-      if (e == hipSuccess) e = pass(lastj ? WP_PASS_EDGE : WP_PASS_AXIS0, a);
+      if (e == hipSuccess) e = pass(lastj ? WP_PASS_EDGE : WP_PASS_AXIS0, a, st);
     }
   } else {
     // K/2 V(t_n + dt/2) K/2 with consecutive kinetic halves merged.
-    e = pass(WP_PASS_EDGE, pass_args(s, 0, wp::OP_FWD | nt_v));
+    e = pass(WP_PASS_EDGE, pass_args(s, 0, wp::OP_FWD | nt_v), st);
     if (e == hipSuccess) e = middle(true);
     for (uint64_t j = 0; j < nsteps && e == hipSuccess; ++j) {
       wp::PassArgs a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | wp::OP_FWD | nt_v);
       e = coef_at((int64_t)(s->step + j), 0.5, &a.coef);
       a.vtau = tau_full;
-      if (e == hipSuccess) e = pass(WP_PASS_AXIS0, a);
+      if (e == hipSuccess) e = pass(WP_PASS_AXIS0, a, st);
       if (e == hipSuccess) e = middle(j + 1 == nsteps);
     }
-    if (e == hipSuccess) e = pass(WP_PASS_EDGE, pass_args(s, 0, wp::OP_PRE_INV | nt_v));
+    if (e == hipSuccess) e = pass(WP_PASS_EDGE, pass_args(s, 0, wp::OP_PRE_INV | nt_v), st);
   }
   return e;
 }
