@@ -243,42 +243,61 @@ def rocprof_summary(base: str, n: int) -> int:
     <name> for name in trace, sq, fetch, write) as markdown on stdout, and
     write base/traffic.json: HBM bytes per full-grid launch of every line-pass
     kernel, each counter scaled by what it reads for the run's 1 GiB device
-    copy (--copy-calibration)."""
+    copy (--copy-calibration).  With the trace alone, prints per-kernel
+    launch counts and times only."""
     import collections
     import re
     import sqlite3
 
     kinds = {"0": "F", "1": "V", "2": "K", "3": "VS", "4": "KS"}
+    heads = {"pass_kernel": "pass", "edge_pass_kernel": "edge", "batch_pass_kernel": "batch"}
 
     def short(name):
-        m = re.match(r"void wp::(edge_)?pass_kernel<(\w+), (\w+), (\d+), (\w+), (\d), (\d)>", name)
-        if m:
+        m = re.match(r"void wp::(\w*pass_kernel)<(\w+), (\w+), (\d+), (\w+), (\d), (\d)>", name)
+        if m and m.group(1) in heads:
             lay = "strided" if m.group(5) == "true" else "contig"
-            head = "edge" if m.group(1) else "pass"
-            return f"{head}<{m.group(2)},{m.group(3)},{m.group(4)},{lay},{kinds[m.group(6)]},t{m.group(7)}>"
+            return f"{heads[m.group(1)]}<{m.group(2)},{m.group(3)},{m.group(4)},{lay},{kinds[m.group(6)]},t{m.group(7)}>"
         return name.split("(")[0].replace("void ", "")[:60]
 
     def db(name):
         return sqlite3.connect(os.path.join(base, name, f"{name}_results.db"))
 
+    if not os.path.exists(os.path.join(base, "sq")):
+        tot = collections.defaultdict(list)
+        for nm, d in db("trace").execute("select name, duration from kernels"):
+            tot[short(nm)].append(d)
+        print("| kernel | launches | avg µs | total ms |")
+        print("|---|---|---|---|")
+        for k, v in sorted(tot.items(), key=lambda kv: -sum(kv[1]))[:40]:
+            print(f"| `{k}` | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {sum(v) / 1e6:.2f} |")
+        return 0
+
     # Launch order of the trace: runs of three or more consecutive launches
-    # of one kernel are back-to-back timing (variant tuning, isolated pass
-    # timing); shorter runs are launches inside steps (two in a row where the
-    # inverse middle pass of one x slab meets the forward pass of the next).
-    seq = [(short(nm), d) for nm, d in db("trace").execute("select name, duration from kernels order by start")]
+    # of one kernel on one stream are back-to-back timing (variant tuning,
+    # isolated pass timing); shorter runs are launches inside steps (two in
+    # a row where the inverse middle pass of one x slab meets the forward
+    # pass of the next).
+    # Runs are counted per stream (the two slab streams interleave).
+    cols = [r[1] for r in db("trace").execute("pragma table_info(kernels)")]
+    skey = next((c for c in ("stream_id", "queue_id") if c in cols), None)
+    q = f"select name, duration, {skey or 0} from kernels order by start"
+    per_stream = collections.defaultdict(list)
+    for nm, d, sid in db("trace").execute(q):
+        per_stream[sid].append((short(nm), d))
     dur = collections.defaultdict(list)
     ctx = collections.defaultdict(lambda: {"step": [], "b2b": []})
     full = {}
-    i = 0
-    while i < len(seq):
-        j = i
-        while j < len(seq) and seq[j][0] == seq[i][0]:
-            j += 1
-        k = seq[i][0]
-        for _, d in seq[i:j]:
-            dur[k].append(d)
-            ctx[k]["step" if j - i < 3 else "b2b"].append(d)
-        i = j
+    for seq in per_stream.values():
+        i = 0
+        while i < len(seq):
+            j = i
+            while j < len(seq) and seq[j][0] == seq[i][0]:
+                j += 1
+            k = seq[i][0]
+            for _, d in seq[i:j]:
+                dur[k].append(d)
+                ctx[k]["step" if j - i < 3 else "b2b"].append(d)
+            i = j
     for nm, in db("trace").execute("select distinct name from kernels"):
         full[short(nm)] = nm
 

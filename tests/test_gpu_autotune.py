@@ -173,3 +173,34 @@ def test_autotune_picks_a_slab_count(S, W):
     assert "slabs" in times and set(times["slabs"]) == {1 << k for k in range(8)}
     assert s.slabs() == min(times["slabs"], key=times["slabs"].get)
     s.close()
+
+
+@pytest.mark.parametrize("count", [2, 8])
+def test_slab_streams_joined_before_caller_work(S, W, count):
+    """Odd slabs run on the handle's second stream; work the caller queues
+    on the handle's stream right after a propagation (no host wait) must see
+    every slab of every step."""
+    import torch
+
+    prob = W.softcore_3d(n=128, steps=0, precision="c64", half_width=10.0)
+    stream = torch.cuda.Stream()
+    s = S.from_problem(prob, stream=stream)
+    s.set_slabs(count)
+    s.synchronize()
+    copies = []
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            s.propagate(4)
+            copies.append(s.buffer.clone())  # queued on the same stream
+    stream.synchronize()
+    final = s.get_state("c64")
+    ref = S.from_problem(prob)
+    ref.set_slabs(1)
+    for i, c in enumerate(copies):
+        ref.propagate(4)
+        want = ref.get_state("c64")
+        got = c.view(torch.complex64).cpu().numpy().reshape(want.shape)
+        assert np.array_equal(got, want), i
+    assert np.array_equal(final, want)
+    s.close()
+    ref.close()
