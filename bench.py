@@ -276,42 +276,46 @@ def rocprof_summary(base: str, n: int) -> int:
     # of one kernel on one stream are back-to-back timing (variant tuning,
     # isolated pass timing); shorter runs are launches inside steps (two in
     # a row where the inverse middle pass of one x slab meets the forward
-    # pass of the next).
-    # Runs are counted per stream (the two slab streams interleave).
-    cols = [r[1] for r in db("trace").execute("pragma table_info(kernels)")]
-    skey = next((c for c in ("stream_id", "queue_id") if c in cols), None)
-    q = f"select name, duration, {skey or 0} from kernels order by start"
+    # pass of the next).  Runs are counted per stream (the two slab streams
+    # interleave).  Rows are per kernel and launch size (grid), so that slab
+    # launches and full-grid launches are not averaged together.
+    def cols(name, view):
+        return [r[1] for r in db(name).execute(f"pragma table_info({view})")]
+
+    tcols = cols("trace", "kernels")
+    skey = next((c for c in ("stream_id", "queue_id") if c in tcols), "0")
+    gkey = next((c for c in ("grid_x", "grid_size") if c in tcols), "0")
     per_stream = collections.defaultdict(list)
-    for nm, d, sid in db("trace").execute(q):
-        per_stream[sid].append((short(nm), d))
+    full = {}
+    for nm, d, sid, g in db("trace").execute(f"select name, duration, {skey}, {gkey} from kernels order by start"):
+        per_stream[sid].append(((short(nm), g), d))
+        full[short(nm)] = nm
     dur = collections.defaultdict(list)
     ctx = collections.defaultdict(lambda: {"step": [], "b2b": []})
-    full = {}
     for seq in per_stream.values():
         i = 0
         while i < len(seq):
             j = i
-            while j < len(seq) and seq[j][0] == seq[i][0]:
+            while j < len(seq) and seq[j][0][0] == seq[i][0][0]:
                 j += 1
-            k = seq[i][0]
-            for _, d in seq[i:j]:
-                dur[k].append(d)
-                ctx[k]["step" if j - i < 3 else "b2b"].append(d)
+            for key, d in seq[i:j]:
+                dur[key].append(d)
+                ctx[key]["step" if j - i < 3 else "b2b"].append(d)
             i = j
-    for nm, in db("trace").execute("select distinct name from kernels"):
-        full[short(nm)] = nm
 
     def counters(name):
+        cc = cols(name, "counters_collection")
+        g = next((c for c in ("grid_size", "grid_x", "grid_size_x") if c in cc), "0")
         per = collections.defaultdict(lambda: collections.defaultdict(list))
-        q = ("select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
+        q = (f"select dispatch_id, kernel_name, counter_name, sum(value), max({g}) from counters_collection "
              "group by dispatch_id, counter_name")
-        for _, k, c, v in db(name).execute(q).fetchall():
-            per[short(k)][c].append(v)
+        for _, k, c, v, gs in db(name).execute(q).fetchall():
+            per[(short(k), gs)][c].append(v)
         return per
 
     sq, fe, wr = counters("sq"), counters("fetch"), counters("write")
     mean = lambda xs: sum(xs) / len(xs) if xs else float("nan")
-    copy = "__amd_rocclr_copyBuffer"
+    copy = next(k for k in fe if k[0] == "__amd_rocclr_copyBuffer")
     kib = (1 << 30) / 1024
     sf = kib / max(fe[copy]["FETCH_SIZE"])
     sw = kib / max(wr[copy]["WRITE_SIZE"])
@@ -319,44 +323,45 @@ def rocprof_summary(base: str, n: int) -> int:
           f"{max(fe[copy]['FETCH_SIZE']):.0f} KiB -> scale {sf:.4f}; WRITE_SIZE reads "
           f"{max(wr[copy]['WRITE_SIZE']):.0f} KiB -> scale {sw:.4f}.")
     print()
-    print("| kernel | launches | avg µs | in-step launches | in-step avg µs | back-to-back avg µs "
+    print("| kernel | part of grid | launches | avg µs | in-step launches | in-step avg µs | back-to-back avg µs "
           "| HBM read GB/launch | HBM write GB/launch | GB/s | LDS conflict cycles / LDS instr | VALU instr / wave |")
-    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|")
     state = 8 * n ** 3
     workload = f"softcore_3d_{n}"
     classes = {"passV": ("axis0",), "edgeV": ("edge",), "passF": ("mid_fwd", "mid_inv"), "passK": ("last",)}
+    gmax = collections.defaultdict(int)
+    for k, g in dur:
+        gmax[k] = max(gmax[k], g)
     entries = {}
-    for k, ds in dur.items():
+    for (k, g), ds in sorted(dur.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
         if "wp::" not in k and "pass<" not in k and "edge<" not in k:
             continue
-        rd = [v * 1024 * sf for v in fe[k]["FETCH_SIZE"]]
-        wt = [v * 1024 * sw for v in wr[k]["WRITE_SIZE"]]
+        rd = [v * 1024 * sf for v in fe[(k, g)]["FETCH_SIZE"]]
+        wt = [v * 1024 * sw for v in wr[(k, g)]["WRITE_SIZE"]]
         r, w = mean(rd) / 1e9, mean(wt) / 1e9
-        q = sq[k]
+        q = sq[(k, g)]
         conf = mean(q["SQ_LDS_BANK_CONFLICT"]) / max(1.0, mean(q["SQ_INSTS_LDS"])) if q["SQ_INSTS_LDS"] else float("nan")
         vpw = mean(q["SQ_INSTS_VALU"]) / max(1.0, mean(q["SQ_WAVES"])) if q["SQ_WAVES"] else float("nan")
-        c = ctx[k]
-        print(f"| `{k}` | {len(ds)} | {mean(ds) / 1e3:.1f} | {len(c['step'])} | "
+        c = ctx[(k, g)]
+        part = "1" if g == gmax[k] else f"1/{gmax[k] // max(1, g)}"
+        print(f"| `{k}` | {part} | {len(ds)} | {mean(ds) / 1e3:.1f} | {len(c['step'])} | "
               f"{mean(c['step']) / 1e3:.1f} | {mean(c['b2b']) / 1e3:.1f} | {r:.3f} | {w:.3f} | "
               f"{(r + w) / (mean(ds) * 1e-9):.0f} | {conf:.3f} | {vpw:.0f} |")
         m = re.match(r"(pass|edge)<float,float,\d+,\w+,(\w+),t(\d)>", k)
         cls = m and classes.get(m.group(1) + m.group(2))
-        if cls and len(rd) == len(wt):
-            # full-grid launches only (slab launches move a fraction of the state)
-            fl = [(a, b) for a, b in zip(rd, wt) if a >= 0.75 * state]
-            if fl:
-                e = {"kernel": full[k], "read_bytes": int(mean([a for a, _ in fl])),
-                     "write_bytes": int(mean([b for _, b in fl])), "launches": len(fl)}
-                e["bytes_per_launch"] = e["read_bytes"] + e["write_bytes"]
-                for cl in cls:
-                    entries[f"{workload}:{cl}:t{m.group(3)}"] = e
+        if cls and rd and wt and g == gmax[k] and mean(rd) >= 0.75 * state:
+            e = {"kernel": full[k], "read_bytes": int(mean(rd)), "write_bytes": int(mean(wt)),
+                 "launches": len(rd), "avg_us": round(mean(ds) / 1e3, 1)}
+            e["bytes_per_launch"] = e["read_bytes"] + e["write_bytes"]
+            for cl in cls:
+                entries[f"{workload}:{cl}:t{m.group(3)}"] = e
     print()
-    print("Raw SQ counters (mean per dispatch):")
+    print("Raw SQ counters (mean per dispatch, per kernel and grid):")
     print()
     print("```")
-    for k, q in sq.items():
+    for (k, g), q in sorted(sq.items()):
         if "pass<" in k or "edge<" in k or "wp::" in k:
-            print(k + ": " + ", ".join(f"{c}={mean(v):.4g}" for c, v in sorted(q.items())))
+            print(f"{k} grid {g}: " + ", ".join(f"{c}={mean(v):.4g}" for c, v in sorted(q.items())))
     print("```")
     with open(os.path.join(base, "traffic.json"), "w") as f:
         json.dump({"kernel_hash": kernel_hash(), "source": "profiles/pass_kernels_softcore_3d_512_c64.md",
@@ -481,7 +486,7 @@ def main() -> int:
     state_bytes = S.state_bytes(prob.grid, "c64")
     alg_bytes = 2 * state_bytes
     nslab = s32.slabs()
-    prof = s32.profile_propagate(args.profile_steps)
+    prof = s32.profile_propagate(max(2, args.profile_steps))  # a steady first-axis pass needs 2 steps
     share = {"axis0": 1, "edge": 1, "mid_fwd": nslab, "last": nslab, "mid_inv": nslab}
     steady = {k: v for k, v in prof.items() if k in (("axis0",) if nslab > 1 else ("axis0", "mid_fwd", "last", "mid_inv"))}
     kind = max(steady, key=lambda k: steady[k][1])
