@@ -443,31 +443,11 @@ def main() -> int:
                            "ms": {c: {str(v): round(m, 4) for v, m in row.items()} for c, row in tuned32.items()},
                            "chosen": {c: min(row, key=row.get) for c, row in tuned32.items()}}
 
-    if not args.no_fp64:
-        # Same start, same number of steps, FP64 state: the FP32 error of this run.
-        s64, ms64, _, tuned64 = time_gpu(S, prob, "c128", args.steps, args.warmup, tune_reps)
-        b = torch.view_as_real(s64.buffer.view(torch.complex128))
-
-        def err(sx):
-            a = torch.view_as_real(sx.buffer.view(torch.complex64)).double()
-            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)), \
-                abs(sx.observables(1)["norm"] - 1.0)
-
-        rel, drift = err(s32)
-        out["fp64"] = {"value": sites * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
-                       "dtype": "f64"}
-        if tuned64:
-            out["fp64"]["autotune_chosen"] = {c: min(row, key=row.get) for c, row in tuned64.items()}
-        out["accuracy"] = {"steps": args.warmup + args.steps, "rel_l2_f32_vs_f64": rel,
-                           "norm_drift_f32": drift, "norm_drift_f64": abs(s64.observables(1)["norm"] - 1.0)}
-        if args.also_c64x:
-            sx, msx, _, _ = time_gpu(S, prob, "c64x", args.steps, args.warmup)
-            relx, driftx = err(sx)
-            out["c64x"] = {"value": sites * args.steps / (msx / 1e3), "ms_per_step": msx / args.steps,
-                           "dtype": "f64 arithmetic, f32 state", "rel_l2_vs_f64": relx, "norm_drift": driftx,
-                           "passes": {k: round(m / c, 4) for k, (c, m) in sx.profile_propagate(4).items()}}
-            sx.close()
-        s64.close()
+    # The state after the timed steps, kept for the FP32-vs-FP64 comparison
+    # below: the roofline run right after (in the conditions of the timed
+    # steps) advances and scrambles the handle's state.
+    state32 = s32.buffer.clone() if not args.no_fp64 else None
+    drift32 = abs(s32.observables(1)["norm"] - 1.0)
 
     # Roofline of the dominant kernel, timed live inside real steps: every
     # launch of `profile_steps` steps carries an event pair attached to its
@@ -520,6 +500,32 @@ def main() -> int:
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
     s32.close()
     torch.cuda.synchronize()
+    if not args.no_fp64:
+        # Same start, same number of steps, FP64 state: the FP32 error of this run.
+        s64, ms64, _, tuned64 = time_gpu(S, prob, "c128", args.steps, args.warmup, tune_reps)
+        b = torch.view_as_real(s64.buffer.view(torch.complex128))
+
+        def err(buf):
+            a = torch.view_as_real(buf.view(torch.complex64)).double()
+            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+        rel, drift = err(state32), drift32
+        out["fp64"] = {"value": sites * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
+                       "dtype": "f64"}
+        if tuned64:
+            out["fp64"]["autotune_chosen"] = {c: min(row, key=row.get) for c, row in tuned64.items()}
+        out["accuracy"] = {"steps": args.warmup + args.steps, "rel_l2_f32_vs_f64": rel,
+                           "norm_drift_f32": drift, "norm_drift_f64": abs(s64.observables(1)["norm"] - 1.0)}
+        if args.also_c64x:
+            sx, msx, _, _ = time_gpu(S, prob, "c64x", args.steps, args.warmup)
+            relx, driftx = err(sx.buffer), abs(sx.observables(1)["norm"] - 1.0)
+            out["c64x"] = {"value": sites * args.steps / (msx / 1e3), "ms_per_step": msx / args.steps,
+                           "dtype": "f64 arithmetic, f32 state", "rel_l2_vs_f64": relx, "norm_drift": driftx,
+                           "passes": {k: round(m / c, 4) for k, (c, m) in sx.profile_propagate(4).items()}}
+            sx.close()
+        s64.close()
+        del state32
+
     if not args.no_batch:
         out["batch"] = batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200,
                                    tune_reps)
