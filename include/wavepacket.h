@@ -217,6 +217,20 @@ wp_status wp_get_state(wp_sim *sim, void *host_out, int32_t as_prec);
  * reference. */
 wp_status wp_observables(wp_sim *sim, uint32_t mask, double *out);
 
+/* Propagate nsteps steps (as wp_propagate) and return the observables of
+ * the final state in out (as wp_observables(sim, mask, out) would): the
+ * algorithm's observables every nprint steps (Algorithm 1, Section 3.2.6).
+ * Norm, <x_d>, <x_d^2> and the widths are accumulated in FP64 by the pass
+ * that ends the propagation, from the values it stores, with no further
+ * read of the state, on power-of-two 2D and 3D grids in the WP_ORDER_VKV
+ * order; other masks, orders and grids run wp_propagate and then
+ * wp_observables.  Sums in a fixed order (deterministic; equal to
+ * wp_observables up to the order of summation).  Allocates one buffer of
+ * 64 bytes per workgroup of that pass on first use.  Synchronises.
+ * WP_EINVAL: NULL out or nsteps not in 1..2^40; otherwise the errors of
+ * wp_propagate and wp_observables. */
+wp_status wp_propagate_observe(wp_sim *sim, uint64_t nsteps, uint32_t mask, double *out);
+
 /* Keep a device copy of the current state as the reference of
  * WP_OBS_AUTOCORR (the initial wave function the autocorrelation of
  * Table 3 compares with; Section 3.5 counts its memory).  Allocates one more

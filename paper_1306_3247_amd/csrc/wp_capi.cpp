@@ -40,6 +40,11 @@ struct wp_sim {
   int slab_lg = 0;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Moment partials of the closing pass (wp_propagate_observe): set for the
+  // duration of one schedule, one 8-slot row per workgroup of that pass.
+  double *moments = nullptr;
+  double *d_mpart = nullptr;
+  int64_t mpart_rows = 0;
   int vdim = 1;
   int vlg[3] = {0, 0, 0};
   int64_t total = 0;
@@ -281,6 +286,7 @@ void release(wp_sim *s) {
   if (s->d_gauss) (void)hipFree(s->d_gauss);
   if (s->ev_gauss) (void)hipEventDestroy(s->ev_gauss);
   if (s->d_wsplit) (void)hipFree(s->d_wsplit);
+  if (s->d_mpart) (void)hipFree(s->d_mpart);
   if (s->side) (void)hipStreamDestroy(s->side);
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
@@ -805,6 +811,7 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
       wp::PassArgs a = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V | (lastj ? 0u : wp::OP_FWD) | nt_v);
       e = coef_at((int64_t)(s->step + j + 1), 0.0, &a.coef);
       a.vtau = lastj ? tau_half : tau_full;
+      if (lastj) a.moments = s->moments;
       if (e == hipSuccess) e = pass(lastj ? WP_PASS_EDGE : WP_PASS_AXIS0, a, st);
     }
   } else {
@@ -1242,6 +1249,66 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
     if (e2 != hipSuccess) return hip_fail(s, e2, "observables");
     all[11] = (o[0] * o[0] + o[1] * o[1]) * dV * dV;
   }
+  int top = 0;
+  for (int i = 0; i < 12; ++i)
+    if (mask & (1u << i)) top = i;
+  for (int i = 0; i <= top; ++i) out[i] = (mask & (1u << i)) ? all[i] : 0.0;
+  s->err.clear();
+  return WP_OK;
+}
+
+wp_status wp_propagate_observe(wp_sim *s, uint64_t nsteps, uint32_t mask, double *out) {
+  if (!s) return WP_EINVAL;
+  if (!out) return fail(s, WP_EINVAL, "propagate_observe: NULL output");
+  if (nsteps == 0 || nsteps > (uint64_t)1 << 40) return fail(s, WP_EINVAL, "propagate_observe: nsteps must be in 1..2^40");
+  constexpr uint32_t kMoments = WP_OBS_NORM | WP_OBS_X | WP_OBS_Y | WP_OBS_Z | WP_OBS_X2 | WP_OBS_Y2 | WP_OBS_Z2 |
+                                WP_OBS_SX | WP_OBS_SY | WP_OBS_SZ;
+  // The closing pass carries the moments on power-of-two 2D/3D grids in the
+  // default order (a first-axis potential pass ends the propagation there);
+  // everything else is a propagation followed by wp_observables.
+  const bool fused = (mask & ~kMoments) == 0 && s->order == WP_ORDER_VKV && s->g.ndim >= 2 && !s->mixed &&
+                     !s->split;
+  if (!fused) {
+    wp_status st = wp_propagate(s, nsteps);
+    return st != WP_OK ? st : wp_observables(s, mask, out);
+  }
+  (void)hipSetDevice(s->device);
+  if (hipError_t e0 = ensure_state(s); e0 != hipSuccess) return state_fail(s, e0, "propagate_observe");
+  const wp::PassArgs probe = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V);
+  const int tile = wp::pass_tile(s->prec, s->vlg[0], true, kind_of(s, 0, probe.ops), probe.tune);
+  if (tile < 1) return fail(s, WP_EUNSUPPORTED, "propagate_observe: no pass for this line length");
+  const int64_t rows = (probe.n_lines + tile - 1) / tile;
+  if (rows > 0x7fffffff) return fail(s, WP_EUNSUPPORTED, "propagate_observe: too many workgroups");
+  hipError_t e = hipSuccess;
+  if (rows > s->mpart_rows) {
+    if (s->d_mpart) {
+      e = hipStreamSynchronize(s->stream);  // earlier reductions may still read it
+      (void)hipFree(s->d_mpart);
+      s->d_mpart = nullptr;
+      s->mpart_rows = 0;
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&s->d_mpart, sizeof(double) * 8 * (size_t)rows);
+    if (e != hipSuccess) return hip_fail(s, e, "propagate_observe");
+    s->mpart_rows = rows;
+  }
+  s->moments = s->d_mpart;
+  e = run_schedule(s, nsteps, [](int, auto &&fn) { return fn(); });
+  s->moments = nullptr;
+  double sums[8];
+  if (e == hipSuccess) e = wp::launch_reduce8(s->d_mpart, (int)rows, s->d_out8, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(sums, s->d_out8, sizeof(sums), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "propagate_observe");
+  s->step += nsteps;
+  double dV = 1.0;
+  for (int d = 0; d < s->g.ndim; ++d) dV *= spacing(s->g, d);
+  double all[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  all[0] = std::sqrt(sums[0] * dV);
+  for (int d = 0; d < s->g.ndim; ++d) {
+    all[1 + d] = sums[1 + d] * dV;
+    all[4 + d] = sums[4 + d] * dV;
+  }
+  for (int d = 0; d < 3; ++d) all[8 + d] = all[4 + d] - all[1 + d] * all[1 + d];
   int top = 0;
   for (int i = 0; i < 12; ++i)
     if (mask & (1u << i)) top = i;

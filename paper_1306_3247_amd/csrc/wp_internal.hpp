@@ -85,6 +85,10 @@ struct PassArgs {
   const cx<double> *wsplit[2];
   int32_t split_h;
   int32_t tune;  // kernel variant (see pass_cfg); 0 = default
+  // Closing first-axis pass only (edge_pass_kernel): if set, workgroup b
+  // also writes the FP64 moment sums of its final values to moments[8b ..]
+  // in the slot layout of the observables' block partials.
+  double *moments;
 };
 
 struct Solve1DArgs {
@@ -185,6 +189,9 @@ hipError_t launch_gsolve1d(int prec, const Solve1DArgs &a, const GPlan &plan, hi
 hipError_t launch_gaussian(int prec, void *psi, const GridDev &g, const cx<double> *f0,
                            const cx<double> *f1, const cx<double> *f2, hipStream_t s);
 hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s);
+// Sum `blocks` rows of 8 partials in index order into out8 (the final step
+// of the observables' reduction).
+hipError_t launch_reduce8(const double *partials, int blocks, double *out8, hipStream_t s);
 // <phi|psi> without dV: out8[0], out8[1] (precisions 1 = complex64, 2 = complex128).
 hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int blocks,
                         double *partials, double *out8, hipStream_t s);

@@ -425,6 +425,11 @@ hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void 
   return hipGetLastError();
 }
 
+hipError_t launch_reduce8(const double *partials, int blocks, double *out8, hipStream_t s) {
+  hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, partials, blocks, out8);
+  return hipGetLastError();
+}
+
 hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *out8, hipStream_t s) {
   if (prec == 2) hipLaunchKernelGGL(obs_kernel<double>, dim3(blocks), dim3(kObsThreads), 0, s, a);
   else hipLaunchKernelGGL(obs_kernel<float>, dim3(blocks), dim3(kObsThreads), 0, s, a);

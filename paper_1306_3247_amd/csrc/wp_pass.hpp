@@ -123,7 +123,7 @@ __device__ __forceinline__ cx<double> split_twiddle(const PassArgs &a, int64_t e
 
 // The work of one workgroup: tile `blk` of the lines described by `a`;
 // `coef` holds the CO_COUNT waveform values at the pass's time (kind V).
-template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
+template <class S, class R, int N, bool STRIDED, int KIND, int TUNE, bool EDGE = false>
 __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef, unsigned blk) {
   using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
   using T = typename storage<S>::type;
@@ -316,6 +316,56 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     if (ops & OP_FWD) line_fft<N, VPT, false>(v, t, tw, lds);  // starts with a barrier
   }
 
+  if constexpr (EDGE && KIND == PK_V && STRIDED) {
+    // Moments of the final values, as the observables define them (the
+    // value as stored, w = |psi|^2 in FP64): the line axis varies per
+    // value, the other axes are constant along the line.  Fixed-order
+    // workgroup tree in the (now idle) line buffer.
+    if (a.moments) {
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+      if (valid) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+          const double pr = (double)(S)v[u].x, pi = (double)(S)v[u].y;
+          const double w = pr * pr + pi * pi;
+          const double x = coord(a.g, a.axis, t + L * u);
+          m0 += w;
+          m1 += x * w;
+          m2 += x * x * w;
+        }
+      }
+      double m[8] = {m0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d == a.axis) {
+          m[1 + d] = m1;
+          m[4 + d] = m2;
+        } else {
+          const double c = coord(a.g, d, idx[d]);
+          m[1 + d] = c * m0;
+          m[4 + d] = c * c * m0;
+        }
+      }
+      // The line buffer holds the tree where it is large enough (every line
+      // length that exchanges through LDS); short lines get their own.
+      constexpr bool OWN = 8 * NT * sizeof(double) > sizeof(s_raw);
+      __shared__ double s_own[OWN ? 8 * NT : 1];
+      double *red = OWN ? s_own : reinterpret_cast<double *>(s_raw);
+      __syncthreads();  // every thread is done with the line buffer
+#pragma unroll
+      for (int k = 0; k < 8; ++k) red[k * NT + tid] = m[k];
+      __syncthreads();
+      for (int h = NT / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) red[k * NT + tid] += red[k * NT + tid + h];
+        }
+        __syncthreads();
+      }
+      if (tid < 8) a.moments[(int64_t)blk * 8 + tid] = red[tid * NT];
+    }
+  }
+
   if (valid && (ops & OP_STORE_NT)) {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) store_nt_from(pt + u * ustep, v[u]);
@@ -336,14 +386,16 @@ __global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND, TUNE>::THREA
 
 // The same first-axis potential pass under its own symbol, for the passes
 // that open or close a propagation (one transform instead of two), so that
-// per-kernel profiles report them apart from the steady-state pass.
+// per-kernel profiles report them apart from the steady-state pass; the
+// closing pass can also reduce the moments of the final state
+// (PassArgs::moments) without touching the steady kernel's registers.
 template <class S, class R, int N, bool STRIDED, int KIND, int TUNE>
 __global__ void __launch_bounds__((pass_cfg<S, R, N, STRIDED, KIND, TUNE>::THREADS),
                                   (pass_cfg<S, R, N, STRIDED, KIND, TUNE>::WAVES_EU))
     edge_pass_kernel(PassArgs a) {
   using C = pass_cfg<S, R, N, STRIDED, KIND, TUNE>;
   const unsigned blk = C::PAIR ? pair_blocks(blockIdx.x, gridDim.x) : blockIdx.x;
-  pass_body<S, R, N, STRIDED, KIND, TUNE>(a, a.coef, blk);
+  pass_body<S, R, N, STRIDED, KIND, TUNE, true>(a, a.coef, blk);
 }
 
 // Batched: workgroup b runs tile items[b].tile of solve items[b].solve, whose

@@ -26,6 +26,8 @@ STATUS = {0: "WP_OK", -1: "WP_EINVAL", -2: "WP_ENOMEM", -3: "WP_EDEVICE",
 OBSERVABLES = ("norm", "x", "y", "z", "x2", "y2", "z2", "energy", "sx", "sy", "sz", "autocorrelation")
 OBS_ALL = 0xFF
 OBS_ALL_EXT = 0xFFF
+OBS_NORM = 0x1
+OBS_MOMENTS = 0x7E | 0x700  # <x_d>, <x_d^2> and the widths
 
 
 class WavepacketError(RuntimeError):
@@ -86,6 +88,7 @@ def _load() -> C.CDLL:
         "wp_set_order": [vp, C.c_int32],
         "wp_get_state": [vp, vp, C.c_int32],
         "wp_observables": [vp, C.c_uint32, P(d)],
+        "wp_propagate_observe": [vp, u64, C.c_uint32, P(d)],
         "wp_get_time": [vp, P(d), P(u64)],
         "wp_synchronize": [vp],
         "wp_profile_propagate": [vp, u64, C.c_uint32, P(d), P(u64)],
@@ -284,6 +287,14 @@ class Simulation:
     def observables(self, mask: int = OBS_ALL) -> dict:
         out = (C.c_double * 12)()
         self._check(lib.wp_observables(self._h, int(mask), out), "wp_observables")
+        return {k: out[i] for i, k in enumerate(OBSERVABLES) if mask & (1 << i)}
+
+    def propagate_observe(self, nsteps: int, mask: int = OBS_NORM | OBS_MOMENTS) -> dict:
+        """Propagate nsteps steps and return the observables of the final
+        state (see wp_propagate_observe: moments come from the pass that
+        ends the propagation where the grid allows)."""
+        out = (C.c_double * 12)()
+        self._check(lib.wp_propagate_observe(self._h, int(nsteps), int(mask), out), "wp_propagate_observe")
         return {k: out[i] for i, k in enumerate(OBSERVABLES) if mask & (1 << i)}
 
     def store_reference(self) -> None:

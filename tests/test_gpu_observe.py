@@ -1,0 +1,140 @@
+"""Observables every nprint steps (wp_propagate_observe): on power-of-two 2D
+and 3D grids in the default order the closing pass accumulates the moments
+of the values it stores; the result equals a propagation followed by
+wp_observables up to the order of FP64 summation, the state and clock are
+those of wp_propagate, and the moments match the oracle's.  Everything else
+falls back to propagation + observables and is identical to it."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+MOMENTS = ("norm", "x", "y", "z", "x2", "y2", "z2", "sx", "sy", "sz")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1306_3247_amd import sim
+
+    return sim
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1306_3247_amd import workloads
+
+    return workloads
+
+
+def fused_case(W, which, precision):
+    if which == "2d":
+        prob = W.modulated_trap_2d(n=256, steps=0, precision=precision, half_width=8.0)
+        return prob, 1, 12
+    if which == "2d_wide":
+        prob = W.modulated_trap_2d(n=64, steps=0, precision=precision, half_width=8.0)
+        prob.grid.n = [8, 1024]  # short first axis: lines of 8 (no LDS exchange)
+        return prob, 1, 5
+    if which == "3d":
+        prob = W.softcore_3d(n=64, steps=0, precision=precision, half_width=5.0)
+        prob.t0 = 9.0
+        return prob, 1, 7
+    prob = W.softcore_3d(n=128, steps=0, precision=precision, half_width=10.0)
+    prob.t0 = 9.0
+    return prob, 8, 5
+
+
+def close(got, ref, keys, rel):
+    scale = max(1.0, max(abs(ref[k]) for k in keys))
+    for k in keys:
+        assert abs(got[k] - ref[k]) <= rel * scale, (k, got[k], ref[k])
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128", "c64x"])
+@pytest.mark.parametrize("which", ["2d", "2d_wide", "3d", "3d_slabs"])
+def test_fused_moments_match_separate(S, W, which, precision):
+    prob, slabs, nsteps = fused_case(W, which, precision)
+    print(f"observe case {which} {precision} grid {prob.grid.n[:prob.grid.ndim]}", flush=True)
+    ref = S.from_problem(prob)
+    got = S.from_problem(prob)
+    if slabs > 1:
+        ref.set_slabs(slabs)
+        got.set_slabs(slabs)
+    mask = S.OBS_NORM | S.OBS_MOMENTS
+    # twice in a row: the partials buffer is reused, the clock advances
+    for _ in range(2):
+        ref.propagate(nsteps)
+        want = ref.observables(mask)
+        have = got.propagate_observe(nsteps, mask)
+        close(have, want, MOMENTS, 1e-13)
+        assert got.time() == ref.time()
+    assert np.array_equal(got.get_state("c128"), ref.get_state("c128"))
+    ref.close()
+    got.close()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_fused_moments_match_oracle(S, W, oracle_mod, precision):
+    prob = W.modulated_trap_2d(n=128, steps=30, precision=precision, half_width=8.0)
+    s = S.from_problem(prob)
+    got = s.propagate_observe(prob.steps, S.OBS_NORM | S.OBS_MOMENTS)
+    t, n = s.time()
+    s.close()
+    assert n == prob.steps
+    psi0 = oracle_mod.gaussian(prob.grid, prob.init.center, prob.init.sigma, prob.init.k)
+    psi = oracle_mod.propagate(prob.grid, prob.pot, psi0, prob.steps, t0=prob.t0)
+    ref = oracle_mod.observables(prob.grid, prob.pot, psi, t)
+    for a, m, m2 in (("sx", "x", "x2"), ("sy", "y", "y2"), ("sz", "z", "z2")):
+        ref[a] = ref[m2] - ref[m] ** 2
+    close(got, ref, MOMENTS, 1e-9 if precision == "c128" else 2e-4)
+
+
+def fallback_sims(S, W, which):
+    if which == "kvk":
+        prob = W.modulated_trap_2d(n=64, steps=0, precision="c128", half_width=8.0)
+        return prob, "kvk"
+    if which == "mixed":
+        prob = W.modulated_trap_2d(n=4, steps=0, precision="c128", half_width=8.0)
+        prob.grid.n = [48, 60]
+        return prob, "vkv"
+    if which == "split":
+        prob = W.driven_trap(1, 1 << 14, E0=0.1, omega=1.0, center=[-2.0], k=[1.0], steps=0, precision="c64",
+                             half_width=20.0)
+        return prob, "vkv"
+    prob = W.driven_ho_1d(n=1024, steps=0, precision="c128")
+    return prob, "vkv"
+
+
+@pytest.mark.parametrize("which", ["kvk", "mixed", "split", "1d"])
+def test_fallback_identical(S, W, which):
+    prob, order = fallback_sims(S, W, which)
+    ref = S.from_problem(prob, order=order)
+    got = S.from_problem(prob, order=order)
+    ref.propagate(6)
+    want = ref.observables(S.OBS_ALL)
+    have = got.propagate_observe(6, S.OBS_ALL)
+    assert have == want
+    assert got.time() == ref.time()
+    ref.close()
+    got.close()
+
+
+def test_energy_mask_falls_back(S, W):
+    """A mask beyond the moments (here the energy) takes the separate path,
+    identical to propagation + observables."""
+    prob = W.softcore_3d(n=32, steps=0, precision="c128", half_width=5.0)
+    ref = S.from_problem(prob)
+    got = S.from_problem(prob)
+    ref.propagate(4)
+    want = ref.observables(S.OBS_ALL)
+    have = got.propagate_observe(4, S.OBS_ALL)
+    assert have == want
+    ref.close()
+    got.close()
+
+
+def test_rejects_bad_arguments(S, W):
+    prob = W.modulated_trap_2d(n=64, steps=0, precision="c64", half_width=8.0)
+    s = S.from_problem(prob)
+    with pytest.raises(S.WavepacketError):
+        s.propagate_observe(0)
+    s.close()
