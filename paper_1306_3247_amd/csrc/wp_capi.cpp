@@ -2,6 +2,7 @@
 // the pass schedule of a step, and observables.  See include/wavepacket.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1351,6 +1352,7 @@ struct PassGroup {
   bool strided;
   uint32_t item_off, nblocks;
   int tune;
+  int lane;
 };
 // The solves of one pass group and their line counts (the block map is
 // rebuilt from this when the group's kernel variant changes).
@@ -1358,7 +1360,13 @@ struct GroupSpec {
   int slot, prec, lgN, kind;
   bool strided;
   std::vector<std::pair<int, int64_t>> members;  // (solve, lines)
+  int lane = 0;
 };
+// Pass groups that share no solve form independent chains across the slots
+// of a step; the steady steps run them on up to kLanes streams (lane 0 is
+// the launching stream), so that small groups fill the gaps and tails of
+// large ones instead of running after them.
+constexpr int kLanes = 3;
 struct Group1D {
   int prec, lgN;
   uint32_t off, count;
@@ -1402,6 +1410,11 @@ struct wp_batch {
   // beside the pass launches instead of before them.
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Lanes of the steady steps (see kLanes): streams and events of lanes
+  // 1 .. lanes-1.
+  int lanes = 1;
+  hipStream_t lane_st[kLanes] = {};
+  hipEvent_t ev_lfork = nullptr, ev_ljoin[kLanes] = {};
   std::string err;
 };
 
@@ -1416,6 +1429,11 @@ void batch_release(wp_batch *b) {
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->side) (void)hipStreamDestroy(b->side);
+  for (int l = 1; l < kLanes; ++l) {
+    if (b->lane_st[l]) (void)hipStreamDestroy(b->lane_st[l]);
+    if (b->ev_ljoin[l]) (void)hipEventDestroy(b->ev_ljoin[l]);
+  }
+  if (b->ev_lfork) (void)hipEventDestroy(b->ev_lfork);
   if (b->ev_step) (void)hipEventDestroy(b->ev_step);
   if (b->h_step) (void)hipHostFree(b->h_step);
   for (void *p : {(void *)b->d_args, (void *)b->d_items, (void *)b->d_args1d, (void *)b->d_pots, (void *)b->d_t0,
@@ -1428,10 +1446,11 @@ wp_status bfail(wp_batch *b, wp_status code, const std::string &msg) {
   return code;
 }
 
-// Launch every pass group of one slot of a step.
-hipError_t run_slot(wp_batch *b, hipStream_t st, int slot, int var, int row) {
+// Launch the pass groups of one slot of a step (of one lane, or of all for
+// lane < 0).
+hipError_t run_slot(wp_batch *b, hipStream_t st, int slot, int var, int row, int lane = -1) {
   for (const PassGroup &g : b->groups) {
-    if (g.slot != slot) continue;
+    if (g.slot != slot || (lane >= 0 && g.lane != lane)) continue;
     wp::BatchLaunch L{};
     L.args = b->d_args;
     L.items = b->d_items + g.item_off;
@@ -1457,7 +1476,7 @@ std::vector<wp::BatchItem> build_items(wp_batch *b) {
   for (const GroupSpec &sp : b->specs) {
     const int tune = wp::effective_tune(sp.prec, sp.lgN, sp.kind, tune_for(1, sp.prec, sp.lgN, sp.strided, sp.kind));
     const int tile = wp::pass_tile(sp.prec, sp.lgN, sp.strided, sp.kind, tune);
-    PassGroup g{sp.slot, sp.prec, sp.lgN, sp.kind, sp.strided, (uint32_t)items.size(), 0, tune};
+    PassGroup g{sp.slot, sp.prec, sp.lgN, sp.kind, sp.strided, (uint32_t)items.size(), 0, tune, sp.lane};
     for (auto &m : sp.members) {
       const int64_t tiles = (m.second + tile - 1) / tile;
       for (int64_t t = 0; t < tiles; ++t) items.push_back({m.first, (int32_t)t});
@@ -1477,16 +1496,68 @@ hipError_t refresh_coef(wp_batch *b, hipStream_t st, int rows) {
 // the merged full potential step and the forward transform of the first
 // axis), then the device step counters advance by k.  Only kernel launches:
 // this is what a graph captures.
+// Lane l > 0 runs on its own stream, forked from `st` after the waveform
+// table is filled and joined back before the counters advance.
 hipError_t steady_steps(wp_batch *b, hipStream_t st, int k) {
   hipError_t e = refresh_coef(b, st, k + 1);
-  for (int j = 0; j < k && e == hipSuccess; ++j) {
-    e = run_slot(b, st, SLOT_FFWD, F_FWD, 0);
-    if (e == hipSuccess) e = run_slot(b, st, SLOT_K, K_LAST, 0);
-    if (e == hipSuccess) e = run_slot(b, st, SLOT_FINV, F_INV, 0);
-    if (e == hipSuccess) e = run_slot(b, st, SLOT_V, V_STEADY, j + 1);
+  if (b->lanes > 1 && e == hipSuccess) {
+    e = hipEventRecord(b->ev_lfork, st);
+    for (int l = 1; l < b->lanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lane_st[l], b->ev_lfork, 0);
+  }
+  for (int l = 0; l < b->lanes && e == hipSuccess; ++l) {
+    const hipStream_t q = l ? b->lane_st[l] : st;
+    const int lane = b->lanes > 1 ? l : -1;
+    for (int j = 0; j < k && e == hipSuccess; ++j) {
+      e = run_slot(b, q, SLOT_FFWD, F_FWD, 0, lane);
+      if (e == hipSuccess) e = run_slot(b, q, SLOT_K, K_LAST, 0, lane);
+      if (e == hipSuccess) e = run_slot(b, q, SLOT_FINV, F_INV, 0, lane);
+      if (e == hipSuccess) e = run_slot(b, q, SLOT_V, V_STEADY, j + 1, lane);
+    }
+  }
+  for (int l = 1; l < b->lanes && e == hipSuccess; ++l) {
+    e = hipEventRecord(b->ev_ljoin[l], b->lane_st[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_ljoin[l], 0);
   }
   if (e == hipSuccess) e = wp::launch_step_advance(b->d_step, (int)b->sims.size(), k, st);
   return e;
+}
+
+// Lanes of the pass groups: groups sharing a solve are joined (union-find),
+// and the resulting chains, largest first, go to the lane with the least
+// work so far (work = lines x line length summed over the chain's groups).
+int assign_lanes(std::vector<GroupSpec> &specs, int nsolves) {
+  const int n = (int)specs.size();
+  std::vector<int> parent(n);
+  for (int i = 0; i < n; ++i) parent[i] = i;
+  auto find = [&](int x) {
+    while (parent[x] != x) x = parent[x] = parent[parent[x]];
+    return x;
+  };
+  std::vector<int> first(nsolves, -1);
+  for (int i = 0; i < n; ++i)
+    for (auto &m : specs[i].members) {
+      if (first[m.first] < 0) first[m.first] = i;
+      else parent[find(i)] = find(first[m.first]);
+    }
+  std::vector<double> work(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (auto &m : specs[i].members) work[find(i)] += (double)m.second * (double)(1 << specs[i].lgN);
+  std::vector<int> roots;
+  for (int i = 0; i < n; ++i)
+    if (find(i) == i) roots.push_back(i);
+  std::sort(roots.begin(), roots.end(), [&](int a, int c) { return work[a] > work[c] || (work[a] == work[c] && a < c); });
+  const int lanes = (int)roots.size() < kLanes ? (int)roots.size() : kLanes;
+  std::vector<double> load(kLanes, 0.0);
+  std::vector<int> lane_of(n, 0);
+  for (int r : roots) {
+    int best = 0;
+    for (int l = 1; l < lanes; ++l)
+      if (load[l] < load[best]) best = l;
+    lane_of[r] = best;
+    load[best] += work[r];
+  }
+  for (int i = 0; i < n; ++i) specs[i].lane = lane_of[find(i)];
+  return lanes < 1 ? 1 : lanes;
 }
 
 }  // namespace
@@ -1570,6 +1641,7 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
   if (e == hipSuccess) {
     for (auto &kv : members)
       b->specs.push_back({kv.first.slot, kv.first.prec, kv.first.lgN, kv.first.kind, kv.first.strided, kv.second});
+    b->lanes = assign_lanes(b->specs, (int)count);
     items = build_items(b);
     for (auto &kv : members1d) {
       Group1D g{kv.first.first, kv.first.second, (uint32_t)a1d.size(), (uint32_t)kv.second.size()};
@@ -1606,6 +1678,13 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+  }
+  if (e == hipSuccess && b->lanes > 1) {
+    e = hipEventCreateWithFlags(&b->ev_lfork, hipEventDisableTiming);
+    for (int l = 1; l < b->lanes && e == hipSuccess; ++l) {
+      e = hipStreamCreateWithFlags(&b->lane_st[l], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_ljoin[l], hipEventDisableTiming);
+    }
   }
   if (e == hipSuccess) e = upload(&b->d_args, args);
   if (e == hipSuccess && !items.empty()) e = upload(&b->d_items, items);
