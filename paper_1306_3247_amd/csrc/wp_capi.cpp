@@ -1000,13 +1000,16 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
     cnc[c] = nc;
     cstrided[c] = a.lg_inner > 0;
     // Two rounds over the candidates, the best of each kept: the first
-    // launches after an idle spell run slower than later ones.
+    // launches after an idle spell run slower than later ones.  Each
+    // candidate starts from a fresh copy of the state (repeated forward
+    // transforms grow the values without bound).
     double tbest[4] = {0, 0, 0, 0};
     for (int round = 0; round < 2 && e == hipSuccess; ++round)
       for (int i = 0; i < nc && e == hipSuccess; ++i) {
         a.tune = cand[i];
         double m = 0.0;
-        e = time_launches(s, a, reps, &m);
+        e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
+        if (e == hipSuccess) e = time_launches(s, a, reps, &m);
         if (e == hipSuccess && (round == 0 || m < tbest[i])) tbest[i] = m;
       }
     int best = 0;
@@ -1019,6 +1022,11 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
     }
     if (e == hipSuccess) tune_store(0, s->prec, lgN, a.lg_inner > 0, kind, best);
   }
+  // The back-to-back launches above leave the scratch copy far from a
+  // solution (repeated unnormalised transforms overflow it), and whole steps
+  // over such data run measurably faster than over a real state: the rounds
+  // below start from a fresh copy of the state.
+  if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
   // Slab count of the middle passes (3D): whole steps on the scratch copy
   // for 1, 2, 4, ... slabs; the state and the step counter are untouched.
   if (e == hipSuccess && s->vdim == 3 && !s->mixed) {
