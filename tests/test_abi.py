@@ -148,3 +148,21 @@ def test_tune_table_host_side(lib):
     assert lib.wp_tune_set(0, 9, 9, 1, 1, 1) == -1
     lib.wp_tune_clear()
     assert lib.wp_tune_get(0, 1, 9, 1, 1, C.byref(out)) == 0 and out.value == 0
+
+
+@pytest.mark.parametrize("lang,flags", [("c", ["-std=c99", "-pedantic"]), ("c++", ["-std=c++17"])])
+def test_headers_compile_as_plain_c_and_cpp(tmp_path, lang, flags):
+    """The boundary is a C ABI: every header compiles on its own as strict C99
+    (no C++ or HIP types leak into it) and as C++, with warnings as errors."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc" if lang == "c" else "g++")
+    if cc is None:
+        pytest.skip(f"no host compiler for {lang}")
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = tmp_path / f"use_{os.path.basename(h)}.{'c' if lang == 'c' else 'cpp'}"
+        src.write_text(f'#include "{os.path.basename(h)}"\nint main(void) {{ return 0; }}\n')
+        r = subprocess.run([cc, *flags, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I",
+                            os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
