@@ -243,6 +243,60 @@ def cpu_baseline(S, prob, budget_s: float):
     return base, parity
 
 
+def small_workloads(S, W, with_oracle: bool):
+    """The cache-resident workloads: the driven 1D oscillator (1024 points,
+    1000 steps, one workgroup holds the line for every step: latency of one
+    solve) and the modulated 2D trap (1024^2, 2000 steps; 8-16 MiB, so the
+    memory-side cache, not HBM, serves it), in FP64 and FP32, against the
+    oracle (W1 at full length, W2 on a sample of steps)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, make in (("driven_ho_1d_1024", W.driven_ho_1d), ("modulated_trap_2d_1024", W.modulated_trap_2d)):
+        row = {}
+        for prec in ("c128", "c64"):
+            prob = make(precision=prec)
+            s = S.from_problem(prob, stream=stream)
+            tuned = s.autotune(10) if prob.grid.ndim > 1 else None
+            s.propagate(min(100, prob.steps))  # warm-up (the state is reset below)
+            s.close()
+            times = []
+            for _ in range(3):
+                s = S.from_problem(prob, stream=stream)
+                s.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                s.propagate(prob.steps)
+                e1.record(stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+                s.close()
+            ms = float(np.median(times))
+            sites = prob.grid.points()
+            row[prec] = {"steps": prob.steps, "ms_total": round(ms, 3), "us_per_step": round(1e3 * ms / prob.steps, 3),
+                         "site_steps_per_s": sites * prob.steps / (ms / 1e3)}
+            if tuned:
+                row[prec]["autotune_chosen"] = {c: min(r, key=r.get) for c, r in tuned.items()}
+            if prob.grid.ndim > 1:
+                bps = 32 if prec == "c64" else 64  # two passes x (read + write) per 2D step
+                row[prec]["bytes_frac_of_hbm_peak"] = round(bps * sites * prob.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        if with_oracle:
+            import oracle
+
+            prob = make(precision="c128")
+            g = prob.grid
+            psi = oracle.gaussian(g, prob.init.center, prob.init.sigma, prob.init.k)
+            n = prob.steps if g.ndim == 1 else 20
+            t = time.perf_counter()
+            oracle.propagate(g, prob.pot, psi, n, t0=prob.t0)
+            el = time.perf_counter() - t
+            row["cpu_oracle"] = {"site_steps_per_s": g.points() * n / el, "steps": n, "cores": oracle.num_threads(),
+                                 "wall_s": round(el, 3)}
+        out[name] = row
+    return out
+
+
 def rocprof_summary(base: str, n: int) -> int:
     """Summarise the four rocprofv3 runs of this benchmark (kernel trace,
     SQ counters, FETCH_SIZE, WRITE_SIZE, written with -d base/<name> -o
@@ -402,6 +456,8 @@ def main() -> int:
     ap.add_argument("--serve-tick", type=int, default=250)
     ap.add_argument("--serve-graph-steps", type=int, default=16)
     ap.add_argument("--serve-budget-gib", type=float, default=192.0)
+    ap.add_argument("--small-workloads", action="store_true",
+                    help="also time the 1D (1024 points) and 2D (1024^2) workloads and their oracle")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--rocprof-summary", metavar="DIR",
@@ -572,6 +628,8 @@ def main() -> int:
         out["serving"] = serve_bench(S, W, V, args.serve_requests, args.serve_warmup, rates,
                                      args.serve_capacity_requests, args.serve_tick, args.serve_graph_steps,
                                      args.serve_budget_gib, 20)
+    if args.small_workloads:
+        out["small_workloads"] = small_workloads(S, W, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["oracle_parity"] = cpu_baseline(S, W.softcore_3d(n=args.n, precision="c128"),
                                                                  args.cpu_seconds)
