@@ -34,6 +34,14 @@ def fused_case(W, which, precision):
         prob = W.modulated_trap_2d(n=64, steps=0, precision=precision, half_width=8.0)
         prob.grid.n = [8, 1024]  # short first axis: lines of 8 (no LDS exchange)
         return prob, 1, 5
+    if which == "2d_short":
+        prob = W.modulated_trap_2d(n=64, steps=0, precision=precision, half_width=8.0)
+        prob.grid.n = [2, 64]  # first axis of 2 points
+        return prob, 1, 4
+    if which == "2d_long":
+        prob = W.modulated_trap_2d(n=64, steps=0, precision=precision, half_width=8.0)
+        prob.grid.n = [4096, 8]  # the longest line the passes take
+        return prob, 1, 3
     if which == "3d":
         prob = W.softcore_3d(n=64, steps=0, precision=precision, half_width=5.0)
         prob.t0 = 9.0
@@ -50,7 +58,7 @@ def close(got, ref, keys, rel):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128", "c64x"])
-@pytest.mark.parametrize("which", ["2d", "2d_wide", "3d", "3d_slabs"])
+@pytest.mark.parametrize("which", ["2d", "2d_wide", "2d_short", "2d_long", "3d", "3d_slabs"])
 def test_fused_moments_match_separate(S, W, which, precision):
     prob, slabs, nsteps = fused_case(W, which, precision)
     print(f"observe case {which} {precision} grid {prob.grid.n[:prob.grid.ndim]}", flush=True)
