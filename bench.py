@@ -508,7 +508,7 @@ def main() -> int:
     # The state after the timed steps, kept for the FP32-vs-FP64 comparison
     # below: the roofline run right after (in the conditions of the timed
     # steps) advances and scrambles the handle's state.
-    state32 = s32.buffer.clone() if not args.no_fp64 else None
+    state32 = s32.state_tensor().clone(memory_format=torch.contiguous_format) if not args.no_fp64 else None
     drift32 = abs(s32.observables(1)["norm"] - 1.0)
 
     # Roofline of the dominant kernel, timed live inside real steps: every
@@ -525,7 +525,7 @@ def main() -> int:
     # it is the class with the most device time per step.  Each class is
     # also launched back to back over the whole grid (wp_time_pass, best of
     # three rounds), kept as passes_back_to_back.
-    state_bytes = S.state_bytes(prob.grid, "c64")
+    state_bytes = prob.grid.points() * 8  # the grid's points, FP32 complex
     alg_bytes = 2 * state_bytes
     nslab = s32.slabs()
     prof = s32.profile_propagate(max(2, args.profile_steps))  # a steady first-axis pass needs 2 steps
@@ -595,10 +595,10 @@ def main() -> int:
     if not args.no_fp64:
         # Same start, same number of steps, FP64 state: the FP32 error of this run.
         s64, ms64, _, tuned64 = time_gpu(S, prob, "c128", args.steps, args.warmup, tune_reps)
-        b = torch.view_as_real(s64.buffer.view(torch.complex128))
+        b = torch.view_as_real(s64.state_tensor())
 
-        def err(buf):
-            a = torch.view_as_real(buf.view(torch.complex64)).double()
+        def err(psi32):
+            a = torch.view_as_real(psi32).double()
             return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
         rel, drift = err(state32), drift32
@@ -610,7 +610,7 @@ def main() -> int:
                            "norm_drift_f32": drift, "norm_drift_f64": abs(s64.observables(1)["norm"] - 1.0)}
         if args.also_c64x:
             sx, msx, _, _ = time_gpu(S, prob, "c64x", args.steps, args.warmup)
-            relx, driftx = err(sx.buffer), abs(sx.observables(1)["norm"] - 1.0)
+            relx, driftx = err(sx.state_tensor()), abs(sx.observables(1)["norm"] - 1.0)
             out["c64x"] = {"value": sites * args.steps / (msx / 1e3), "ms_per_step": msx / args.steps,
                            "dtype": "f64 arithmetic, f32 state", "rel_l2_vs_f64": relx, "norm_drift": driftx,
                            "passes": {k: round(m / c, 4) for k, (c, m) in sx.profile_propagate(4).items()}}

@@ -27,7 +27,11 @@
  *     unused axes have n = 1.  Boundaries are periodic.
  *   - State psi: row-major [n0][n1][n2] (last axis contiguous), interleaved
  *     (re, im).  WP_C128 stores two doubles per point, WP_C64 and WP_C64X
- *     two floats.
+ *     two floats.  In device memory the planes of the first axis start
+ *     wp_state_pitch points apart: n1*n2, except on 3D grids whose lengths
+ *     are all powers of two, where 16 unused points follow every plane (so
+ *     that a first-axis line does not meet the memory at one power-of-two
+ *     stride).  Host buffers are always contiguous.
  *     The FP32 path keeps phase arguments, coordinates, time and every
  *     reduction in FP64 and multiplies by FP64-accurate factors.
  *   - Streams: all device work of a handle is ordered on the HIP stream
@@ -136,9 +140,15 @@ enum {
   WP_OBS_ALL_EXT = 0xfffu
 };
 
-/* Device bytes of the state for this grid (n0*n1*n2 * 8 or 16).
- * WP_EINVAL for an invalid descriptor. */
+/* Device bytes of the state for this grid (n0 * pitch * 8 or 16, pitch as
+ * wp_state_pitch reports it).  WP_EINVAL for an invalid descriptor. */
 wp_status wp_state_bytes(const wp_grid_desc *grid, uint64_t *bytes);
+
+/* Points between the starts of consecutive first-axis planes of the state
+ * in device memory (*pitch >= n1*n2; point (i0, i1, i2) is at
+ * i0*pitch + i1*n2 + i2).  The points after each plane's n1*n2 are never
+ * read or written.  WP_EINVAL for an invalid descriptor or NULL. */
+wp_status wp_state_pitch(const wp_grid_desc *grid, uint64_t *pitch);
 
 /* Device bytes wp_create allocates for this grid in total, state included
  * (state, per-axis kinetic and twiddle tables).  An energy request later
@@ -169,7 +179,8 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
 wp_status wp_destroy(wp_sim *sim);
 
 /* Use caller-owned device memory `dev_psi` (at least wp_state_bytes, 16-byte
- * aligned) as the state from now on; work queued afterwards uses it.  A
+ * aligned; planes wp_state_pitch points apart) as the state from now on;
+ * work queued afterwards uses it.  A
  * state buffer the library allocated before is freed after waiting for the
  * handle's stream (only then does the call synchronise).  The caller keeps
  * ownership and must keep the memory alive until wp_destroy.  The content
@@ -239,9 +250,10 @@ wp_status wp_store_reference(wp_sim *sim);
 
 /* <phi|psi> = sum conj(phi) psi dV over the grid (`integrate3D` of Section
  * 3.2.6 with f1 = phi, f2 = the current state; the projection onto a
- * given state of Section 3.2.5).  dev_phi: device memory in the state's
- * layout, WP_C64 (complex64) or WP_C128 (complex128) per phi_prec,
- * caller-owned and only read.  out[0], out[1]: real and imaginary part.
+ * given state of Section 3.2.5).  dev_phi: device memory holding the n0*n1*n2
+ * points contiguously in row-major order (no plane padding), WP_C64
+ * (complex64) or WP_C128 (complex128) per phi_prec, caller-owned and only
+ * read.  out[0], out[1]: real and imaginary part.
  * FP64 deterministic reduction.  Synchronises.  WP_EINVAL: NULL pointer or
  * bad precision. */
 wp_status wp_inner(wp_sim *sim, const void *dev_phi, int32_t phi_prec, double *out);

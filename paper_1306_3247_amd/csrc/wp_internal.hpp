@@ -32,7 +32,17 @@ struct GridDev {
   double lo[3], dx[3];
   int32_t n[3];   // axis lengths (1 on unused axes)
   int32_t pow2;   // every length a power of two: indices by shifts, else by division
+  // Storage: point i of the row-major grid sits at i + (i >> lg_plane) * pad,
+  // i.e. consecutive first-axis planes of 2^lg_plane points lie
+  // 2^lg_plane + pad points apart (pad = 0: contiguous).
+  int32_t lg_plane;
+  int32_t pad;
 };
+
+// Storage position of point i of the row-major grid.
+__device__ __forceinline__ int64_t phys_index(const GridDev &g, int64_t i) {
+  return i + (i >> g.lg_plane) * (int64_t)g.pad;
+}
 
 // Indices (i0, i1, i2) of point i of the row-major [n0][n1][n2] grid.
 __device__ __forceinline__ void grid_index(const GridDev &g, int64_t i, int &i0, int &i1, int &i2) {
@@ -192,9 +202,11 @@ hipError_t launch_observables(int prec, const ObsArgs &a, int blocks, double *ou
 // Sum `blocks` rows of 8 partials in index order into out8 (the final step
 // of the observables' reduction).
 hipError_t launch_reduce8(const double *partials, int blocks, double *out8, hipStream_t s);
-// <phi|psi> without dV: out8[0], out8[1] (precisions 1 = complex64, 2 = complex128).
-hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int blocks,
-                        double *partials, double *out8, hipStream_t s);
+// <phi|psi> without dV over `total` points: out8[0], out8[1] (precisions
+// 1 = complex64, 2 = complex128); point i of phi (psi) is stored at
+// i + (i >> lg_plane) * phi_pad (psi_pad).
+hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int lg_plane,
+                        int phi_pad, int psi_pad, int blocks, double *partials, double *out8, hipStream_t s);
 // Waveform values for `count` consecutive steps: out[j*CO_COUNT + w] is
 // waveform w at the time of step T.step + j (plus T.half).
 hipError_t launch_coefficients(const PotDev &p, const TimeDev &T, int count, double *out, hipStream_t s);

@@ -283,7 +283,7 @@ __global__ void gaussian_kernel(void *out, GridDev g, const cx<double> *f0, cons
     int i0, i1, i2;
     grid_index(g, i, i0, i1, i2);
     const cx<double> f = cmul(cmul(f0[i0], f1[i1]), f2[i2]);
-    store_from(psi + i, f);
+    store_from(psi + phys_index(g, i), f);
   }
 }
 
@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(kObsThreads) obs_kernel(ObsArgs a) {
 
   for (int64_t i = (int64_t)blockIdx.x * kObsThreads + tid; i < a.total;
        i += (int64_t)gridDim.x * kObsThreads) {
-    const T p = psi[i];
+    const T p = psi[phys_index(a.g, i)];
     const double pr = p.x, pi = p.y;
     const double w = pr * pr + pi * pi;
     int i0, i1, i2;
@@ -386,7 +386,8 @@ __global__ void __launch_bounds__(kObsThreads) obs_final_kernel(const double *pa
 // eight slots (the layout obs_final_kernel reduces), same fixed order.
 template <class RP, class RS>
 __global__ void __launch_bounds__(kObsThreads)
-    inner_kernel(const void *phi_, const void *psi_, int64_t total, double *partials) {
+    inner_kernel(const void *phi_, const void *psi_, int64_t total, int lg_plane, int phi_pad, int psi_pad,
+                 double *partials) {
   using TP = typename storage<RP>::type;
   using TS = typename storage<RS>::type;
   __shared__ double s_red[2][kObsThreads];
@@ -395,7 +396,10 @@ __global__ void __launch_bounds__(kObsThreads)
   const int tid = threadIdx.x;
   double re = 0.0, im = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kObsThreads + tid; i < total; i += (int64_t)gridDim.x * kObsThreads) {
-    const double ar = phi[i].x, ai = phi[i].y, br = psi[i].x, bi = psi[i].y;
+    const int64_t plane = i >> lg_plane;
+    const TP a = phi[i + plane * phi_pad];
+    const TS b = psi[i + plane * psi_pad];
+    const double ar = a.x, ai = a.y, br = b.x, bi = b.y;
     re += ar * br + ai * bi;
     im += ar * bi - ai * br;
   }
@@ -412,13 +416,17 @@ __global__ void __launch_bounds__(kObsThreads)
   if (tid < 8) partials[(int64_t)blockIdx.x * 8 + tid] = tid < 2 ? s_red[tid][0] : 0.0;
 }
 
-hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int blocks,
-                        double *partials, double *out8, hipStream_t s) {
+hipError_t launch_inner(int phi_prec, const void *phi, int psi_prec, const void *psi, int64_t total, int lg_plane,
+                        int phi_pad, int psi_pad, int blocks, double *partials, double *out8, hipStream_t s) {
   const dim3 g(blocks), b(kObsThreads);
-  if (phi_prec == 2 && psi_prec == 2) hipLaunchKernelGGL((inner_kernel<double, double>), g, b, 0, s, phi, psi, total, partials);
-  else if (phi_prec == 2) hipLaunchKernelGGL((inner_kernel<double, float>), g, b, 0, s, phi, psi, total, partials);
-  else if (psi_prec == 2) hipLaunchKernelGGL((inner_kernel<float, double>), g, b, 0, s, phi, psi, total, partials);
-  else hipLaunchKernelGGL((inner_kernel<float, float>), g, b, 0, s, phi, psi, total, partials);
+  if (phi_prec == 2 && psi_prec == 2)
+    hipLaunchKernelGGL((inner_kernel<double, double>), g, b, 0, s, phi, psi, total, lg_plane, phi_pad, psi_pad, partials);
+  else if (phi_prec == 2)
+    hipLaunchKernelGGL((inner_kernel<double, float>), g, b, 0, s, phi, psi, total, lg_plane, phi_pad, psi_pad, partials);
+  else if (psi_prec == 2)
+    hipLaunchKernelGGL((inner_kernel<float, double>), g, b, 0, s, phi, psi, total, lg_plane, phi_pad, psi_pad, partials);
+  else
+    hipLaunchKernelGGL((inner_kernel<float, float>), g, b, 0, s, phi, psi, total, lg_plane, phi_pad, psi_pad, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, (const double *)partials, blocks, out8);

@@ -144,9 +144,12 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
   const int64_t o = line >> lgi, c = line & (((int64_t)1 << lgi) - 1);
   const int64_t base = (o << (fft_shape<N>::lg + lgi)) + c;
   // Element t + L*u of this thread's line is at pt + u*ustep (ustep is the
-  // same for the whole workgroup).
-  T *const pt = (T *)a.psi + base + ((int64_t)t << lgi);
-  const int64_t ustep = (int64_t)L << lgi;
+  // same for the whole workgroup).  A line of the first axis crosses the
+  // planes, whose storage lies 2^lgi + pad points apart; the lines of the
+  // other axes stay inside one plane.
+  const int64_t lstride = STRIDED ? ((int64_t)1 << lgi) + (a.axis == 0 ? (int64_t)a.g.pad : 0) : 1;
+  T *const pt = (T *)a.psi + phys_index(a.g, base) + t * lstride;
+  const int64_t ustep = (int64_t)L * lstride;
   const uint32_t ops = a.ops;
 
   cx<R> v[VPT];

@@ -160,7 +160,11 @@ class Server:
         keep = self.keep_results
         if keep is True or (keep and rec.rid in keep):
             dt = np.complex128 if job.prob.precision == "c128" else np.complex64
-            rec.result = job.host.numpy().view(dt).reshape(job.sim.shape).copy()
+            shape = job.sim.shape
+            pitch = _sim.state_pitch(job.prob.grid, job.prob.precision)
+            plane = int(np.prod(shape[1:]))
+            flat = job.host.numpy().view(dt)[: shape[0] * pitch]
+            rec.result = flat.reshape(shape[0], pitch)[:, :plane].reshape(shape).copy()
         job.host = None
 
     # -- the loop ----------------------------------------------------------

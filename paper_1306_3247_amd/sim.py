@@ -78,6 +78,7 @@ def _load() -> C.CDLL:
     P, vp, u64, d = C.POINTER, C.c_void_p, C.c_uint64, C.c_double
     sig = {
         "wp_state_bytes": [P(GridDesc), P(u64)],
+        "wp_state_pitch": [P(GridDesc), P(u64)],
         "wp_workspace_bytes": [P(GridDesc), P(u64)],
         "wp_create": [P(GridDesc), P(PotentialDesc), vp, P(vp)],
         "wp_destroy": [vp],
@@ -167,6 +168,15 @@ def state_bytes(grid, precision: str) -> int:
     rc = lib.wp_state_bytes(C.byref(grid_desc(grid, precision)), C.byref(out))
     if rc:
         raise WavepacketError(rc, "wp_state_bytes")
+    return out.value
+
+
+def state_pitch(grid, precision: str) -> int:
+    """Points between the first-axis planes of the state in device memory."""
+    out = C.c_uint64()
+    rc = lib.wp_state_pitch(C.byref(grid_desc(grid, precision)), C.byref(out))
+    if rc:
+        raise WavepacketError(rc, "wp_state_pitch")
     return out.value
 
 
@@ -377,6 +387,21 @@ class Simulation:
 
     def state_ptr(self) -> int:
         return lib.wp_state_ptr(self._h)
+
+    def state_tensor(self):
+        """The state in device memory as a complex tensor of the grid's shape
+        (a strided view of the bound buffer, no copy): complex128 for the
+        FP64 state, complex64 otherwise."""
+        import torch
+
+        dt = torch.complex128 if self.precision == "c128" else torch.complex64
+        flat = self.buffer.view(dt)
+        n0 = self.shape[0]
+        plane = int(np.prod(self.shape[1:])) if len(self.shape) > 1 else 1
+        pitch = state_pitch(self.grid, self.precision)
+        strides = [pitch] + [int(np.prod(self.shape[d + 1:])) for d in range(1, len(self.shape))]
+        assert flat.numel() >= (n0 - 1) * pitch + plane
+        return flat.as_strided(self.shape, strides)
 
 
 def from_problem(prob, precision: Optional[str] = None, stream=None, order: str = "vkv") -> Simulation:

@@ -64,15 +64,41 @@ def _state_bytes(lib, desc):
     return rc, out.value
 
 
+def _pitch(lib, desc):
+    out = C.c_uint64()
+    rc = lib.wp_state_pitch(C.byref(desc), C.byref(out))
+    return rc, out.value
+
+
 def test_state_and_workspace_bytes(lib):
+    # 3D power-of-two grid: 16 unused points after every x plane
     d = _desc(_grid(), "c64")
     rc, b = _state_bytes(lib, d)
-    assert rc == 0 and b == 8 * 16 * 4 * 8
+    assert rc == 0 and b == 8 * (16 * 4 + 16) * 8
     d = _desc(_grid(), "c128")
     rc, b = _state_bytes(lib, d)
-    assert rc == 0 and b == 8 * 16 * 4 * 16
+    assert rc == 0 and b == 8 * (16 * 4 + 16) * 16
     out = C.c_uint64()
     assert lib.wp_workspace_bytes(C.byref(d), C.byref(out)) == 0 and out.value > b
+
+
+@pytest.mark.parametrize("kw,pitch", [
+    (dict(), 16 * 4 + 16),                                     # 3D, powers of two: padded planes
+    (dict(n=[512, 512, 512]), 512 * 512 + 16),
+    (dict(n=[6, 10, 14]), 10 * 14),                             # a length not a power of two
+    (dict(n=[8, 12, 4]), 12 * 4),
+    (dict(ndim=2, n=[64, 32, 1]), 32),                          # 2D and 1D: contiguous
+    (dict(ndim=1, n=[1 << 16, 1, 1]), 1),
+])
+def test_state_pitch(lib, kw, pitch):
+    for prec, elem in (("c64", 8), ("c128", 16), ("c64x", 8)):
+        d = _desc(_grid(**kw), prec)
+        rc, p = _pitch(lib, d)
+        assert rc == 0 and p == pitch
+        rc, b = _state_bytes(lib, d)
+        assert rc == 0 and b == d.n[0] * pitch * elem
+    assert lib.wp_state_pitch(C.byref(_desc(_grid(ndim=4))), C.byref(C.c_uint64())) == -1
+    assert lib.wp_state_pitch(C.byref(_desc(_grid())), None) == -1
 
 
 @pytest.mark.parametrize("bad", [

@@ -191,7 +191,7 @@ def test_slab_streams_joined_before_caller_work(S, W, count):
     with torch.cuda.stream(stream):
         for _ in range(3):
             s.propagate(4)
-            copies.append(s.buffer.clone())  # queued on the same stream
+            copies.append(s.state_tensor().clone(memory_format=torch.contiguous_format))  # same stream
     stream.synchronize()
     final = s.get_state("c64")
     ref = S.from_problem(prob)
@@ -199,7 +199,7 @@ def test_slab_streams_joined_before_caller_work(S, W, count):
     for i, c in enumerate(copies):
         ref.propagate(4)
         want = ref.get_state("c64")
-        got = c.view(torch.complex64).cpu().numpy().reshape(want.shape)
+        got = c.cpu().numpy().reshape(want.shape)
         assert np.array_equal(got, want), i
     assert np.array_equal(final, want)
     s.close()

@@ -54,8 +54,8 @@ def test_softcore_512_full_length_fp32_vs_fp64(S, W):
     for s in (a, b):
         s.propagate(2000)
         s.synchronize()
-    x = torch.view_as_real(a.buffer.view(torch.complex64)).double()
-    y = torch.view_as_real(b.buffer.view(torch.complex128))
+    x = torch.view_as_real(a.state_tensor()).double()
+    y = torch.view_as_real(b.state_tensor())
     rel = float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
     n32, n64 = a.observables(1)["norm"], b.observables(1)["norm"]
     print(f"512^3 x 2000: rel_l2(f32, f64) = {rel:.3e}, norm drift f32 {abs(n32 - 1):.3e}, f64 {abs(n64 - 1):.3e}")
