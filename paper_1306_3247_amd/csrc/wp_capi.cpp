@@ -627,10 +627,16 @@ void *wp_state_ptr(wp_sim *s) { return s ? s->psi : nullptr; }
 hipError_t copy_state(const wp_sim *s, void *dst, const void *src, size_t elem, bool to_device) {
   const size_t rows = (size_t)s->g.n[0];
   const size_t row = (size_t)(s->total / (int64_t)rows) * elem, pitch = (size_t)s->pitch * elem;
-  if (row == pitch)
-    return hipMemcpyAsync(dst, src, rows * row, to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost, s->stream);
-  return to_device ? hipMemcpy2DAsync(dst, pitch, src, row, row, rows, hipMemcpyHostToDevice, s->stream)
-                   : hipMemcpy2DAsync(dst, row, src, pitch, row, rows, hipMemcpyDeviceToHost, s->stream);
+  const hipMemcpyKind kind = to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+  if (row == pitch) return hipMemcpyAsync(dst, src, rows * row, kind, s->stream);
+  // One copy per plane, contiguous on both sides.  (A pitched 2D copy from
+  // pageable host memory returned zeros under rocprofv3 at 512^3.)
+  const size_t dstep = to_device ? pitch : row, sstep = to_device ? row : pitch;
+  for (size_t r = 0; r < rows; ++r) {
+    hipError_t e = hipMemcpyAsync((char *)dst + r * dstep, (const char *)src + r * sstep, row, kind, s->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 wp_status wp_set_state(wp_sim *s, const double *host, double t0) {
