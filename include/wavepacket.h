@@ -187,7 +187,8 @@ wp_status wp_destroy(wp_sim *sim);
  * is not changed.  Errors: WP_EINVAL (NULL, too small or misaligned). */
 wp_status wp_bind_state(wp_sim *sim, void *dev_psi, uint64_t bytes);
 
-/* Device pointer of the current state (library-owned or bound). */
+/* Device pointer of the current state (library-owned or bound), laid out
+ * with the plane pitch of wp_state_pitch. */
 void *wp_state_ptr(wp_sim *sim);
 
 /* Copy a host state (row-major, complex128, n0*n1*n2 points) to the device,
