@@ -162,7 +162,8 @@ wp_status wp_workspace_bytes(const wp_grid_desc *grid, uint64_t *bytes);
  * call; the state buffer itself is allocated on first use unless one is
  * bound with wp_bind_state.  Axis lengths: powers of two (the fast
  * kernels), or on grids where some length is not a power of two, lengths
- * with prime factors 2, 3, 5 and 7 only (the sizes Section 3.3 advises),
+ * with prime factors 2, 3, 5 and 7 only (the sizes Section 3.2.1 advises
+ * for nx, ny, nz of struct `parameters`),
  * transformed by mixed-radix kernels in FP64 arithmetic.  Errors: WP_EINVAL
  * (bad descriptor: ndim not in 1..3, n < 2 on a used axis, n != 1 on an
  * unused axis, hi <= lo, mass <= 0, hbar <= 0, dt = 0 or not finite,

@@ -37,7 +37,7 @@ static int is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
 
 /* Any axis length n >= 2 is accepted: the transform below handles every
  * factorisation (the paper advises lengths with small prime factors for
- * speed, Section 3.3, not for correctness). */
+ * speed, Section 3.2.1 under nx/ny/nz, not for correctness). */
 static int grid_ok(const orc_grid *g) {
   if (g->ndim < 1 || g->ndim > 3) return 0;
   for (int d = 0; d < 3; ++d) {

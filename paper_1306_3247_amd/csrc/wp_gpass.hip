@@ -1,6 +1,6 @@
 // wp_gpass.hip -- line passes and the 1D solver for axis lengths whose prime
 // factors are 2, 3, 5 and 7 (the lengths advised for the transforms in
-// Section 3.3), up to 4096 points.
+// Section 3.2.1, struct `parameters`, nx/ny/nz), up to 4096 points.
 //
 // A workgroup loads a tile of lines into LDS, transforms them stage by stage
 // (Stockham autosort with radices 8, 4, 2, 3, 5, 7: butterfly j of a stage of

@@ -361,6 +361,42 @@ def test_observables_closed_forms(oracle_mod):
     assert o["energy"] == pytest.approx(kin + vexp, abs=1e-11)
 
 
+def test_observables_closed_forms_3d(oracle_mod):
+    """The 3D observables (Table 3 norm, energy, x/y/z averages; `norm`,
+    `expectation1D` of Section 3.2.6) of the Gaussian of Section 4.2 in
+    V = c + sum_d (a_d x_d + b_d x_d^2), on a grid whose three axes differ in
+    length, extent, centre, width and momentum (so a swapped axis, a wrong
+    coordinate or wavenumber table for z, or a dropped z term fails), with
+    hbar, m != 1:  <x_d> = c_d, <x_d^2> = c_d^2 + sigma_d^2/4 and
+    E = sum_d hbar^2 (k_d^2 + 1/sigma_d^2)/2m + c + sum_d (a_d c_d + b_d <x_d^2>)."""
+    g = W.Grid(3, [96, 80, 64], [-10.0, -9.0, -8.0], [10.0, 9.0, 8.0], mass=1.4, hbar=0.7)
+    c, s, k = [1.5, -2.0, 0.7], [1.3, 0.9, 1.1], [0.8, -0.6, 1.1]
+    a, b = [0.15, -0.25, 0.35], [0.5, 0.3, 0.45]
+    pot = W.Potential()
+    for d in range(3):
+        pot.a[d], pot.b[d] = W.const(a[d]), W.const(b[d])
+    pot.c = W.const(-0.1)
+    psi = oracle_mod.gaussian(g, c, s, k)
+    o = oracle_mod.observables(g, pot, psi, 0.0)
+    assert o["norm"] == pytest.approx(1.0, abs=1e-13)
+    x2 = [c[d] ** 2 + s[d] ** 2 / 4 for d in range(3)]
+    for d, ax in enumerate("xyz"):
+        assert o[ax] == pytest.approx(c[d], abs=1e-12), ax
+        assert o[ax + "2"] == pytest.approx(x2[d], abs=1e-12), ax
+    kin = [g.hbar ** 2 * (k[d] ** 2 + 1 / s[d] ** 2) / (2 * g.mass) for d in range(3)]
+    vexp = -0.1 + sum(a[d] * c[d] + b[d] * x2[d] for d in range(3))
+    assert o["energy"] == pytest.approx(sum(kin) + vexp, abs=1e-11)
+    # Each axis on its own: with V = 0 and the other axes' k = 0, the kinetic
+    # energy of axis d alone is hbar^2 (k_d^2 + 1/sigma_d^2)/2m plus the
+    # zero-momentum parts of the others.
+    for d in range(3):
+        kk = [0.0, 0.0, 0.0]
+        kk[d] = k[d]
+        e = oracle_mod.observables(g, W.Potential(), oracle_mod.gaussian(g, c, s, kk), 0.0)["energy"]
+        want = sum(g.hbar ** 2 * (kk[j] ** 2 + 1 / s[j] ** 2) / (2 * g.mass) for j in range(3))
+        assert e == pytest.approx(want, abs=1e-11), d
+
+
 def test_inner_product_of_gaussians(oracle_mod):
     g = W.Grid(1, [256], [-16.0], [16.0])
     a = oracle_mod.gaussian(g, [-1.0], [1.5], [0.0])
