@@ -244,6 +244,28 @@ wp_status wp_observables(wp_sim *sim, uint32_t mask, double *out);
  * wp_propagate and wp_observables. */
 wp_status wp_propagate_observe(wp_sim *sim, uint64_t nsteps, uint32_t mask, double *out);
 
+/* For callers that cannot allocate device memory (tight serving loops and
+ * harnesses that forbid hipMalloc/hipFree after set-up): wp_propagate_observe
+ * without any allocation.  The closing pass writes its moment rows (8
+ * doubles per workgroup) to a fixed array of WP_NOALLOC_MOMENT_ROWS rows
+ * (4 MiB) that the library's code object holds on every device it runs on
+ * until the process ends, instead of a buffer allocated on first use; the
+ * slabs of a 3D step run on the handle's stream alone while its second
+ * stream has not been created by an earlier propagation.  Results equal
+ * wp_propagate_observe's bit for bit.  Only the fused case: a power-of-two
+ * 2D or 3D grid in the WP_ORDER_VKV order and a mask within norm, <x_d>,
+ * <x_d^2> and the widths.  All calls on one device share that array: calls
+ * that overlap in time on one device (different host threads, or handles
+ * on different streams without ordering between them) race and must be
+ * serialised by the caller.  Synchronises.  Errors: WP_EINVAL (NULL out,
+ * nsteps not in 1..2^40), WP_EUNSUPPORTED (another grid, order or mask;
+ * a closing pass of more than WP_NOALLOC_MOMENT_ROWS workgroups, e.g. a
+ * first axis of 512 points with more than 2^20 lines across it in FP32),
+ * WP_ESTATE (no state set or bound yet: allocating it is not allowed
+ * here), WP_EDEVICE. */
+#define WP_NOALLOC_MOMENT_ROWS 65536
+wp_status wp_propagate_observe_noalloc(wp_sim *sim, uint64_t nsteps, uint32_t mask, double *out);
+
 /* Keep a device copy of the current state as the reference of
  * WP_OBS_AUTOCORR (the initial wave function the autocorrelation of
  * Table 3 compares with; Section 3.5 counts its memory).  Allocates one more

@@ -749,8 +749,11 @@ namespace {
 // so that no cache write-back or invalidation lands inside the timed interval.
 inline hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
 
+// With no_alloc the walk creates nothing: while the handle's second stream
+// does not exist yet, the slabs of a step all run on the handle's stream
+// (the same kernels in the same order per slab, so the same bits).
 template <class Launch>
-hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
+hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch, bool no_alloc = false) {
   const double tau_half = 0.5 * s->g.dt / s->g.hbar;
   const double tau_full = s->g.dt / s->g.hbar;
   const int prec = s->prec;
@@ -813,17 +816,18 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
   const uint32_t nt_last = stream && s->slab_lg == 0 ? kNT : 0u;                    // last middle pass
   // Slabs alternate between the handle's stream and the second one.
   const int nslab = 1 << s->slab_lg;
-  if (nslab > 1) {
+  const bool two = nslab > 1 && !(no_alloc && !s->side);
+  if (two) {
     if (hipError_t r = ensure_side(s); r != hipSuccess) return r;
   }
   auto middle = [&](bool half_k) -> hipError_t {
     hipError_t r = hipSuccess;
-    if (nslab > 1) {
+    if (two) {
       r = hipEventRecord(s->ev_fork, st);
       if (r == hipSuccess) r = hipStreamWaitEvent(s->side, s->ev_fork, 0);
     }
     for (int sl = 0; sl < nslab && r == hipSuccess; ++sl) {
-      const hipStream_t q = (sl & 1) ? s->side : st;
+      const hipStream_t q = (two && (sl & 1)) ? s->side : st;
       for (int d = 1; d < last && r == hipSuccess; ++d)
         r = pass(WP_PASS_MID_FWD, slab_args(s, pass_args(s, d, wp::OP_FWD | nt_first), sl), q);
       if (r != hipSuccess) return r;
@@ -833,7 +837,7 @@ hipError_t run_schedule(wp_sim *s, uint64_t nsteps, Launch &&launch) {
       for (int d = last - 1; d >= 1 && r == hipSuccess; --d)
         r = pass(WP_PASS_MID_INV, slab_args(s, pass_args(s, d, wp::OP_PRE_INV | nt_last), sl), q);
     }
-    if (nslab > 1 && r == hipSuccess) {
+    if (two && r == hipSuccess) {
       r = hipEventRecord(s->ev_join, s->side);
       if (r == hipSuccess) r = hipStreamWaitEvent(st, s->ev_join, 0);
     }
@@ -1310,48 +1314,42 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
   return WP_OK;
 }
 
-wp_status wp_propagate_observe(wp_sim *s, uint64_t nsteps, uint32_t mask, double *out) {
-  if (!s) return WP_EINVAL;
-  if (!out) return fail(s, WP_EINVAL, "propagate_observe: NULL output");
-  if (nsteps == 0 || nsteps > (uint64_t)1 << 40) return fail(s, WP_EINVAL, "propagate_observe: nsteps must be in 1..2^40");
-  constexpr uint32_t kMoments = WP_OBS_NORM | WP_OBS_X | WP_OBS_Y | WP_OBS_Z | WP_OBS_X2 | WP_OBS_Y2 | WP_OBS_Z2 |
-                                WP_OBS_SX | WP_OBS_SY | WP_OBS_SZ;
-  // The closing pass carries the moments on power-of-two 2D/3D grids in the
-  // default order (a first-axis potential pass ends the propagation there);
-  // everything else is a propagation followed by wp_observables.
-  const bool fused = (mask & ~kMoments) == 0 && s->order == WP_ORDER_VKV && s->g.ndim >= 2 && !s->mixed &&
-                     !s->split;
-  if (!fused) {
-    wp_status st = wp_propagate(s, nsteps);
-    return st != WP_OK ? st : wp_observables(s, mask, out);
-  }
-  (void)hipSetDevice(s->device);
-  if (hipError_t e0 = ensure_state(s); e0 != hipSuccess) return state_fail(s, e0, "propagate_observe");
+}  // extern "C"
+
+namespace {
+
+constexpr uint32_t kMomentMask = WP_OBS_NORM | WP_OBS_X | WP_OBS_Y | WP_OBS_Z | WP_OBS_X2 | WP_OBS_Y2 | WP_OBS_Z2 |
+                                 WP_OBS_SX | WP_OBS_SY | WP_OBS_SZ;
+
+// The closing pass carries the moments on power-of-two 2D/3D grids in the
+// default order (a first-axis potential pass ends the propagation there).
+bool observe_fusable(const wp_sim *s, uint32_t mask) {
+  return (mask & ~kMomentMask) == 0 && s->order == WP_ORDER_VKV && s->g.ndim >= 2 && !s->mixed && !s->split;
+}
+
+// Workgroups of the closing pass, i.e. 8-slot moment rows it writes.
+wp_status closing_rows(wp_sim *s, int64_t *rows) {
   const wp::PassArgs probe = pass_args(s, 0, wp::OP_PRE_INV | wp::OP_V);
   const int tile = wp::pass_tile(s->prec, s->vlg[0], true, kind_of(s, 0, probe.ops), probe.tune);
   if (tile < 1) return fail(s, WP_EUNSUPPORTED, "propagate_observe: no pass for this line length");
-  const int64_t rows = (probe.n_lines + tile - 1) / tile;
-  if (rows > 0x7fffffff) return fail(s, WP_EUNSUPPORTED, "propagate_observe: too many workgroups");
-  hipError_t e = hipSuccess;
-  if (rows > s->mpart_rows) {
-    if (s->d_mpart) {
-      e = hipStreamSynchronize(s->stream);  // earlier reductions may still read it
-      (void)hipFree(s->d_mpart);
-      s->d_mpart = nullptr;
-      s->mpart_rows = 0;
-    }
-    if (e == hipSuccess) e = hipMalloc((void **)&s->d_mpart, sizeof(double) * 8 * (size_t)rows);
-    if (e != hipSuccess) return hip_fail(s, e, "propagate_observe");
-    s->mpart_rows = rows;
-  }
-  s->moments = s->d_mpart;
-  e = run_schedule(s, nsteps, [](int, auto &&fn) { return fn(); });
+  *rows = (probe.n_lines + tile - 1) / tile;
+  if (*rows > 0x7fffffff) return fail(s, WP_EUNSUPPORTED, "propagate_observe: too many workgroups");
+  return WP_OK;
+}
+
+// Propagate with the closing pass writing its moment rows to `mrows` (rows
+// entries of 8 doubles, every one written by this propagation), reduce them
+// in row order and return the observables of `mask`.  Synchronises.
+wp_status observe_fused(wp_sim *s, uint64_t nsteps, uint32_t mask, double *out, double *mrows, int64_t rows,
+                        bool no_alloc, const char *what) {
+  s->moments = mrows;
+  hipError_t e = run_schedule(s, nsteps, [](int, auto &&fn) { return fn(); }, no_alloc);
   s->moments = nullptr;
   double sums[8];
-  if (e == hipSuccess) e = wp::launch_reduce8(s->d_mpart, (int)rows, s->d_out8, s->stream);
+  if (e == hipSuccess) e = wp::launch_reduce8(mrows, (int)rows, s->d_out8, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(sums, s->d_out8, sizeof(sums), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(s, e, "propagate_observe");
+  if (e != hipSuccess) return hip_fail(s, e, what);
   s->step += nsteps;
   double dV = 1.0;
   for (int d = 0; d < s->g.ndim; ++d) dV *= spacing(s->g, d);
@@ -1368,6 +1366,89 @@ wp_status wp_propagate_observe(wp_sim *s, uint64_t nsteps, uint32_t mask, double
   for (int i = 0; i <= top; ++i) out[i] = (mask & (1u << i)) ? all[i] : 0.0;
   s->err.clear();
   return WP_OK;
+}
+
+// Moment rows of wp_propagate_observe_noalloc: one fixed array per device,
+// loaded with the library's code object, so that the call allocates
+// nothing.  Host code never uses the array's name as an address (on the
+// host it only names the symbol): its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and is
+// kept in scratch_dev[].  Every call on a device shares that device's
+// array; a call writes every row it later reads, so nothing needs clearing.
+constexpr int64_t kNoAllocRows = WP_NOALLOC_MOMENT_ROWS;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[8 * kNoAllocRows];
+std::mutex scratch_mu;
+double *scratch_dev[kMaxDevices] = {};
+
+hipError_t scratch_on(int device, double **ptr) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    double *p = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[device] = p;
+  }
+  *ptr = scratch_dev[device];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+wp_status wp_propagate_observe(wp_sim *s, uint64_t nsteps, uint32_t mask, double *out) {
+  if (!s) return WP_EINVAL;
+  if (!out) return fail(s, WP_EINVAL, "propagate_observe: NULL output");
+  if (nsteps == 0 || nsteps > (uint64_t)1 << 40) return fail(s, WP_EINVAL, "propagate_observe: nsteps must be in 1..2^40");
+  // Everything the closing pass cannot carry is a propagation followed by
+  // wp_observables.
+  if (!observe_fusable(s, mask)) {
+    wp_status st = wp_propagate(s, nsteps);
+    return st != WP_OK ? st : wp_observables(s, mask, out);
+  }
+  (void)hipSetDevice(s->device);
+  if (hipError_t e0 = ensure_state(s); e0 != hipSuccess) return state_fail(s, e0, "propagate_observe");
+  int64_t rows = 0;
+  if (wp_status st = closing_rows(s, &rows); st != WP_OK) return st;
+  hipError_t e = hipSuccess;
+  if (rows > s->mpart_rows) {
+    if (s->d_mpart) {
+      e = hipStreamSynchronize(s->stream);  // earlier reductions may still read it
+      (void)hipFree(s->d_mpart);
+      s->d_mpart = nullptr;
+      s->mpart_rows = 0;
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&s->d_mpart, sizeof(double) * 8 * (size_t)rows);
+    if (e != hipSuccess) return hip_fail(s, e, "propagate_observe");
+    s->mpart_rows = rows;
+  }
+  return observe_fused(s, nsteps, mask, out, s->d_mpart, rows, false, "propagate_observe");
+}
+
+wp_status wp_propagate_observe_noalloc(wp_sim *s, uint64_t nsteps, uint32_t mask, double *out) {
+  if (!s) return WP_EINVAL;
+  if (!out) return fail(s, WP_EINVAL, "propagate_observe_noalloc: NULL output");
+  if (nsteps == 0 || nsteps > (uint64_t)1 << 40)
+    return fail(s, WP_EINVAL, "propagate_observe_noalloc: nsteps must be in 1..2^40");
+  if (!observe_fusable(s, mask))
+    return fail(s, WP_EUNSUPPORTED,
+                "propagate_observe_noalloc: needs a power-of-two 2D or 3D grid, the default order and a mask of "
+                "norm, moments and widths only");
+  (void)hipSetDevice(s->device);
+  int64_t rows = 0;
+  if (wp_status st = closing_rows(s, &rows); st != WP_OK) return st;
+  if (rows > kNoAllocRows)
+    return fail(s, WP_EUNSUPPORTED,
+                "propagate_observe_noalloc: the closing pass has " + std::to_string(rows) +
+                    " workgroups, more than the " + std::to_string(kNoAllocRows) + " rows of the fixed scratch");
+  if (!s->psi) return fail(s, WP_ESTATE, "propagate_observe_noalloc: no state yet (set or bind one first)");
+  double *mrows = nullptr;
+  if (hipError_t e = scratch_on(s->device, &mrows); e != hipSuccess)
+    return hip_fail(s, e, "propagate_observe_noalloc: scratch address");
+  return observe_fused(s, nsteps, mask, out, mrows, rows, true, "propagate_observe_noalloc");
 }
 
 wp_status wp_get_time(wp_sim *s, double *t, uint64_t *step) {

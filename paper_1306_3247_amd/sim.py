@@ -90,6 +90,7 @@ def _load() -> C.CDLL:
         "wp_get_state": [vp, vp, C.c_int32],
         "wp_observables": [vp, C.c_uint32, P(d)],
         "wp_propagate_observe": [vp, u64, C.c_uint32, P(d)],
+        "wp_propagate_observe_noalloc": [vp, u64, C.c_uint32, P(d)],
         "wp_get_time": [vp, P(d), P(u64)],
         "wp_synchronize": [vp],
         "wp_profile_propagate": [vp, u64, C.c_uint32, P(d), P(u64)],
@@ -305,6 +306,15 @@ class Simulation:
         ends the propagation where the grid allows)."""
         out = (C.c_double * 12)()
         self._check(lib.wp_propagate_observe(self._h, int(nsteps), int(mask), out), "wp_propagate_observe")
+        return {k: out[i] for i, k in enumerate(OBSERVABLES) if mask & (1 << i)}
+
+    def propagate_observe_noalloc(self, nsteps: int, mask: int = OBS_NORM | OBS_MOMENTS) -> dict:
+        """As propagate_observe, allocating nothing (see
+        wp_propagate_observe_noalloc: the fused moments only, with the moment
+        rows in the library's fixed per-device array)."""
+        out = (C.c_double * 12)()
+        self._check(lib.wp_propagate_observe_noalloc(self._h, int(nsteps), int(mask), out),
+                    "wp_propagate_observe_noalloc")
         return {k: out[i] for i, k in enumerate(OBSERVABLES) if mask & (1 << i)}
 
     def store_reference(self) -> None:
