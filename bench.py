@@ -32,7 +32,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("paper_1306_3247_amd/csrc/wp_kernels.hip", "paper_1306_3247_amd/csrc/wp_device.hpp",
                   "paper_1306_3247_amd/csrc/wp_internal.hpp", "paper_1306_3247_amd/csrc/wp_pass.hpp",
                   "paper_1306_3247_amd/csrc/wp_pass_c64.hip", "paper_1306_3247_amd/csrc/wp_pass_c64_t1.hip",
-                  "paper_1306_3247_amd/csrc/wp_pass_c64_t2.hip", "paper_1306_3247_amd/csrc/wp_pass_c64_t3.hip")
+                  "paper_1306_3247_amd/csrc/wp_pass_c64_t2.hip", "paper_1306_3247_amd/csrc/wp_pass_c64_t3.hip",
+                  "paper_1306_3247_amd/csrc/wp_pass_c128.hip", "paper_1306_3247_amd/csrc/wp_pass_c128_t2.hip")
+BYTES_PER_POINT = {"c64": 8, "c128": 16}
 
 
 def kernel_hash() -> str:
@@ -43,7 +45,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kind: str, workload: str, tune: int = 0):
+def traffic_for(kind: str, workload: str, precision: str, tune: int = 0):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel sources; else None."""
     try:
@@ -53,8 +55,120 @@ def traffic_for(kind: str, workload: str, tune: int = 0):
         return None
     if t.get("kernel_hash") != kernel_hash():
         return None
-    e = t.get("entries", {}).get(f"{workload}:{kind}:t{tune}")
+    e = t.get("entries", {}).get(f"{workload}:{precision}:{kind}:t{tune}")
     return None if e is None else e.get("bytes_per_launch")
+
+
+def roofline_of(S, s, precision: str, prob, workload: str, warmup: int, profile_steps: int, pass_reps: int):
+    """Roofline of the dominant kernel of a handle's step, timed live inside
+    real steps: every launch of `profile_steps` steps carries an event pair
+    attached to its own dispatch (wp_profile_propagate), so the pair spans
+    exactly that kernel and nothing is enqueued between kernels.  A
+    first-axis pass covers the whole grid; a middle pass covers one x slab
+    of it.  Each pass reads and writes its part of the state once: the
+    algorithmic bytes of a launch are 2 x the bytes it covers.  With more
+    than one slab the slabs alternate between two streams, so middle-pass
+    launches overlap and their in-step durations are not device time per
+    step; the dominant kernel is then the potential pass of the first axis,
+    the largest kernel of a step and the one that runs alone.  With one
+    slab it is the class with the most device time per step.  Each class is
+    also launched back to back over the whole grid (wp_time_pass, best of
+    three rounds, each from a fresh copy of the solution: repeated
+    unnormalised transforms grow the values until they overflow, and passes
+    over such data run faster than over a real state).  Leaves the handle's
+    state advanced by warmup + profile_steps steps, then overwritten by the
+    pass timing (not a solution afterwards)."""
+    state_bytes = prob.grid.points() * BYTES_PER_POINT[precision]
+    alg_bytes = 2 * state_bytes
+    nslab = s.slabs()
+    # Warm-up steps queued right before the profiled ones, as before the
+    # timed region: after a pause (a host copy) the first-axis launches of a
+    # short profiled run measured 0.65-0.67 ms against 0.57-0.59 ms without
+    # it (same box; the timed steps and repeats unaffected).
+    s.propagate(warmup)
+    prof = s.profile_propagate(max(2, profile_steps))  # a steady first-axis pass needs 2 steps
+    share = {"axis0": 1, "edge": 1, "mid_fwd": nslab, "last": nslab, "mid_inv": nslab}
+    steady = {k: v for k, v in prof.items() if k in (("axis0",) if nslab > 1 else ("axis0", "mid_fwd", "last", "mid_inv"))}
+    kind = max(steady, key=lambda k: steady[k][1])
+    count, total_ms = steady[kind]
+    avg_ms = total_ms / count
+    launch_bytes = alg_bytes // share[kind]
+    achieved = launch_bytes / (avg_ms / 1e3) / 1e9
+    fresh = s.buffer.clone()
+
+    def time_fresh(k):
+        s.buffer.copy_(fresh)
+        return s.time_pass(k, pass_reps)
+
+    timed = {k: min(time_fresh(k) for _ in range(3)) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
+    del fresh
+    lg = int(np.log2(prob.grid.n[0]))
+    tp = "c128" if precision == "c128" else "c64"
+    variant = {"axis0": S.tune_get(False, tp, lg, True, "potential"),
+               "mid_fwd": S.tune_get(False, tp, lg, True, "fft"),
+               "mid_inv": S.tune_get(False, tp, lg, True, "fft"),
+               "last": S.tune_get(False, tp, lg, False, "kinetic")}
+    traffic = traffic_for(kind, workload, precision, variant[kind]) if share[kind] == 1 else None
+    return {"bound": "hbm", "kernel": f"pass:{kind}", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "variant": variant[kind], "avg_launch_ms": round(avg_ms, 4),
+            "launches": count, "alg_bytes_per_launch": launch_bytes, "slabs": nslab,
+            "timing": "in-step, dispatch-attached events",
+            "passes_in_step": {k: {"launches": c, "avg_ms": round(m / c, 4),
+                                   "GB/s": round(alg_bytes / share.get(k, 1) / (m / c / 1e3) / 1e9, 1)
+                                   if k in share else None}
+                               for k, (c, m) in prof.items()},
+            "passes_back_to_back": {k: {"avg_ms": round(m, 4), "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)}
+                                    for k, m in timed.items()},
+            "back_to_back_reps": pass_reps}
+
+
+def copy_bandwidth(gib: int = 1, reps: int = 10) -> dict:
+    """A plain device-to-device copy of `gib` GiB (torch's copy kernel): the
+    read-and-write bandwidth a streaming kernel can reach on this machine."""
+    import torch
+
+    src = torch.ones(gib << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * src.numel() * 4
+    del src, dst
+    return {"bytes_per_copy": moved, "ms": round(ms, 4), "GB/s": round(moved / (ms / 1e3) / 1e9, 1),
+            "frac_of_peak": round(moved / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def full_length_accuracy(S, W, n: int, steps: int) -> dict:
+    """The stated run of the 3D workload from the Gaussian start: `steps`
+    steps in FP32 and in FP64 (the FP64 state is pinned to the oracle), the
+    FP32 error against it over every point, and both norm drifts."""
+    import torch
+
+    prob = W.softcore_3d(n=n, steps=steps)
+    a = S.from_problem(prob, precision="c64")
+    b = S.from_problem(prob, precision="c128")
+    t = time.perf_counter()
+    for x in (a, b):
+        x.propagate(steps)
+        x.synchronize()
+    el = time.perf_counter() - t
+    d = torch.view_as_real(a.state_tensor()).double() - torch.view_as_real(b.state_tensor())
+    rel = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(torch.view_as_real(b.state_tensor())))
+    del d
+    n32, n64 = a.observables(1)["norm"], b.observables(1)["norm"]
+    a.close()
+    b.close()
+    torch.cuda.synchronize()
+    return {"steps": steps, "t_end": prob.t0 + steps * prob.grid.dt, "rel_l2_f32_vs_f64": rel,
+            "norm_drift_f32": abs(n32 - 1.0), "norm_drift_f64": abs(n64 - 1.0),
+            "bound_rel_l2_f32": 1e-4, "bound_norm_drift_f32": 1e-5, "wall_s": round(el, 2)}
 
 
 def time_gpu(sim_mod, prob, precision, steps, warmup, tune_reps=0):
@@ -140,11 +254,14 @@ def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int,
 
 
 def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int, graph_steps: int,
-                budget_gib: float, ref_count: int):
+                budget_gib: float, ref_count: int, sweep_seconds: float = 0.0):
     """The serving workload: Poisson request streams (60% 1D 2^10..2^16, 30%
     2D 128..1024^2, 10% 3D 64..256^3, 500..5000 steps, FP32 state) served with
     admission by HBM budget and continuous batching.  Rates are fractions of
-    the closed-loop capacity (every request present at time zero)."""
+    the closed-loop capacity (every request present at time zero).  A stream
+    at rate f*C takes about (warm + count)/(f*C) seconds; if the sweep would
+    take longer than sweep_seconds, warm and count are scaled down by the
+    same factor for every rate (the counts used are reported)."""
     import torch
 
     kw = dict(budget_bytes=int(budget_gib * (1 << 30)), tick_steps=tick, graph_steps=graph_steps)
@@ -163,6 +280,11 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
     mix = W.serving_stream(5000, float("inf"), seed=7)
     mean_work = float(np.mean([r.problem.grid.points() * r.problem.steps for r in mix]))
     C = cap["site_steps_per_s"] / mean_work
+    asked = (count, warm)
+    projected = sum((warm + count) / (f * C) for f in rates)
+    if sweep_seconds > 0 and projected > sweep_seconds:
+        scale = sweep_seconds / projected
+        count, warm = max(100, int(count * scale)), max(10, int(warm * scale))
     runs = []
     for i, f in enumerate(rates):
         reqs = W.serving_stream(warm + count, f * C, seed=1306 + 1 + i)
@@ -196,7 +318,9 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
         errs.append(float(np.linalg.norm(x.result.astype(np.complex128) - y) / np.linalg.norm(y)))
     best = max(runs, key=lambda z: z["site_steps_per_s"])
     return {"workload": "serving_poisson_mixed", "capacity_req_per_s": C, "mean_site_steps_per_request": mean_work,
-            "capacity": cap,
+            "capacity": cap, "requests_per_rate": count, "warmup_per_rate": warm,
+            "requests_per_rate_asked": asked[0], "warmup_per_rate_asked": asked[1],
+            "sweep_projected_s": round(projected, 1), "sweep_limit_s": sweep_seconds,
             "runs": runs, "tick_steps": tick, "graph_steps": graph_steps, "budget_gib": budget_gib,
             "per_solve_fp64": {"value": ref_rate, "unit": "site-steps/s",
                                "sample": f"first {ref_count} requests of the closed-loop stream, one after another"},
@@ -297,14 +421,19 @@ def small_workloads(S, W, with_oracle: bool):
     return out
 
 
-def rocprof_summary(base: str, n: int) -> int:
+def rocprof_summary(base: str, n: int, precision: str = "all") -> int:
     """Summarise the four rocprofv3 runs of this benchmark (kernel trace,
     SQ counters, FETCH_SIZE, WRITE_SIZE, written with -d base/<name> -o
     <name> for name in trace, sq, fetch, write) as markdown on stdout, and
     write base/traffic.json: HBM bytes per full-grid launch of every line-pass
     kernel, each counter scaled by what it reads for the run's 1 GiB device
     copy (--copy-calibration).  With the trace alone, prints per-kernel
-    launch counts and times only."""
+    launch counts and times only.  precision "c64" or "c128" keeps the
+    tables to the line passes of that state type (traffic.json keeps all)."""
+    keep_type = {"c64": "<float,", "c128": "<double,"}.get(precision)
+
+    def shown(k):
+        return keep_type is None or keep_type in k or not k.startswith(("pass<", "edge<", "batch<"))
     import collections
     import re
     import sqlite3
@@ -365,6 +494,8 @@ def rocprof_summary(base: str, n: int) -> int:
         others = sorted((kv for kv in dur.items() if not kv[0][0].startswith(("pass<", "edge<"))),
                         key=lambda kv: -sum(kv[1]))[:20]
         for (k, g), ds in passes + others:
+            if not shown(k):
+                continue
             c = ctx[(k, g)]
             print(f"| `{k}` | {g} | {len(ds)} | {mean(ds) / 1e3:.1f} | {sum(ds) / 1e6:.2f} | "
                   f"{len(c['step'])} | {mean(c['step']) / 1e3:.1f} | {mean(c['b2b']) / 1e3:.1f} |")
@@ -392,9 +523,10 @@ def rocprof_summary(base: str, n: int) -> int:
     print("| kernel | part of grid | launches | avg µs | in-step launches | in-step avg µs | back-to-back avg µs "
           "| HBM read GB/launch | HBM write GB/launch | GB/s | LDS conflict cycles / LDS instr | VALU instr / wave |")
     print("|---|---|---|---|---|---|---|---|---|---|---|---|")
-    state = 8 * n ** 3
     workload = f"softcore_3d_{n}"
     classes = {"passV": ("axis0",), "edgeV": ("edge",), "passF": ("mid_fwd", "mid_inv"), "passK": ("last",)}
+    # storage type of a pass kernel -> precision of the handle and bytes of its state
+    prec_of = {"float": ("c64", 8 * n ** 3), "double": ("c128", 16 * n ** 3)}
     gmax = collections.defaultdict(int)
     for k, g in dur:
         gmax[k] = max(gmax[k], g)
@@ -410,27 +542,31 @@ def rocprof_summary(base: str, n: int) -> int:
         vpw = mean(q["SQ_INSTS_VALU"]) / max(1.0, mean(q["SQ_WAVES"])) if q["SQ_WAVES"] else float("nan")
         c = ctx[(k, g)]
         part = "1" if g == gmax[k] else f"1/{gmax[k] // max(1, g)}"
-        print(f"| `{k}` | {part} | {len(ds)} | {mean(ds) / 1e3:.1f} | {len(c['step'])} | "
-              f"{mean(c['step']) / 1e3:.1f} | {mean(c['b2b']) / 1e3:.1f} | {r:.3f} | {w:.3f} | "
-              f"{(r + w) / (mean(ds) * 1e-9):.0f} | {conf:.3f} | {vpw:.0f} |")
-        m = re.match(r"(pass|edge)<float,float,\d+,\w+,(\w+),t(\d)>", k)
-        cls = m and classes.get(m.group(1) + m.group(2))
+        if shown(k):
+            print(f"| `{k}` | {part} | {len(ds)} | {mean(ds) / 1e3:.1f} | {len(c['step'])} | "
+                  f"{mean(c['step']) / 1e3:.1f} | {mean(c['b2b']) / 1e3:.1f} | {r:.3f} | {w:.3f} | "
+                  f"{(r + w) / (mean(ds) * 1e-9):.0f} | {conf:.3f} | {vpw:.0f} |")
+        m = re.match(r"(pass|edge)<(float|double),(float|double),\d+,\w+,(\w+),t(\d)>", k)
+        cls = m and classes.get(m.group(1) + m.group(4))
+        prec, state = prec_of[m.group(2)] if m else (None, 0)
+        if m and m.group(2) == "float" and m.group(3) == "double":
+            prec = "c64x"
         if cls and rd and wt and g == gmax[k] and mean(rd) >= 0.75 * state:
             e = {"kernel": full[k], "read_bytes": int(mean(rd)), "write_bytes": int(mean(wt)),
                  "launches": len(rd), "avg_us": round(mean(ds) / 1e3, 1)}
             e["bytes_per_launch"] = e["read_bytes"] + e["write_bytes"]
             for cl in cls:
-                entries[f"{workload}:{cl}:t{m.group(3)}"] = e
+                entries[f"{workload}:{prec}:{cl}:t{m.group(5)}"] = e
     print()
     print("Raw SQ counters (mean per dispatch, per kernel and grid):")
     print()
     print("```")
     for (k, g), q in sorted(sq.items()):
-        if "pass<" in k or "edge<" in k or "wp::" in k:
+        if ("pass<" in k or "edge<" in k or "wp::" in k) and shown(k):
             print(f"{k} grid {g}: " + ", ".join(f"{c}={mean(v):.4g}" for c, v in sorted(q.items())))
     print("```")
     with open(os.path.join(base, "traffic.json"), "w") as f:
-        json.dump({"kernel_hash": kernel_hash(), "source": "profiles/pass_kernels_softcore_3d_512_c64.md",
+        json.dump({"kernel_hash": kernel_hash(), "source": "profiles/pass_kernels_softcore_3d_512_*.md",
                    "scale": {"FETCH_SIZE": round(sf, 4), "WRITE_SIZE": round(sw, 4)}, "entries": entries},
                   f, indent=1)
     return 0
@@ -455,9 +591,15 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-graph-steps", type=int, default=16)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300, help="measured requests per arrival rate")
-    ap.add_argument("--serve-warmup", type=int, default=30, help="requests served before the measured ones")
-    ap.add_argument("--serve-rates", type=str, default="0.5,0.9", help="fractions of the closed-loop capacity")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="measured requests per arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="requests served before the measured ones")
+    ap.add_argument("--serve-rates", type=str, default="0.25,0.5,0.75,0.9,1.1",
+                    help="fractions of the closed-loop capacity")
+    ap.add_argument("--serve-seconds", type=float, default=180.0,
+                    help="projected wall time of the arrival-rate sweep: if the asked request counts would take "
+                         "longer at the measured capacity, they are scaled down alike for every rate (0: no limit)")
+    ap.add_argument("--accuracy-steps", type=int, default=2000,
+                    help="steps of the full-length FP32-vs-FP64 run of the 3D workload (0: skip)")
     ap.add_argument("--serve-capacity-requests", type=int, default=200)
     ap.add_argument("--serve-tick", type=int, default=250)
     ap.add_argument("--serve-graph-steps", type=int, default=16)
@@ -466,11 +608,13 @@ def main() -> int:
                     help="also time the 1D (1024 points) and 2D (1024^2) workloads and their oracle")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--summary-precision", choices=("all", "c64", "c128"), default="all",
+                    help="with --rocprof-summary: tables of the line passes of this state type only")
     ap.add_argument("--rocprof-summary", metavar="DIR",
                     help="summarise the rocprofv3 runs under DIR (no GPU work) and exit")
     args = ap.parse_args()
     if args.rocprof_summary:
-        return rocprof_summary(args.rocprof_summary, args.n)
+        return rocprof_summary(args.rocprof_summary, args.n, args.summary_precision)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -512,46 +656,14 @@ def main() -> int:
                            "chosen": {c: min(row, key=row.get) for c, row in tuned32.items()}}
 
     # The state after the timed steps, kept (in host memory) for the
-    # FP32-vs-FP64 comparison below: the roofline run advances the handle's
-    # state.
+    # FP32-vs-FP64 comparison of the timed run below: the roofline run
+    # advances the handle's state.
     state32 = s32.get_state("c64") if not args.no_fp64 else None
     drift32 = abs(s32.observables(1)["norm"] - 1.0)
-
-    # Roofline of the dominant kernel, timed live inside real steps: every
-    # launch of `profile_steps` steps carries an event pair attached to its
-    # own dispatch (wp_profile_propagate), so the pair spans exactly that
-    # kernel and nothing is enqueued between kernels.  A first-axis pass
-    # covers the whole grid; a middle pass covers one x slab of it.  Each
-    # pass reads and writes its part of the state once: the algorithmic bytes
-    # of a launch are 2 x the bytes it covers.  With more than one slab the
-    # slabs alternate between two streams, so middle-pass launches overlap
-    # and their in-step durations are not device time per step; the
-    # dominant kernel is then the potential pass of the first axis, the
-    # largest kernel of a step and the one that runs alone.  With one slab
-    # it is the class with the most device time per step.  Each class is
-    # also launched back to back over the whole grid (wp_time_pass, best of
-    # three rounds), kept as passes_back_to_back.
-    state_bytes = prob.grid.points() * 8  # the grid's points, FP32 complex
-    alg_bytes = 2 * state_bytes
-    nslab = s32.slabs()
-    # Warm-up steps queued right before the profiled ones, as before the
-    # timed region: after the pause of the copy above the first-axis launches
-    # of a short profiled run measured 0.65-0.67 ms against 0.57-0.59 ms
-    # without the pause (same box; the timed steps and repeats unaffected).
+    # The timed region again, five more times, continuing the same solution
+    # (after warm-up steps queued without a pause, as before the timed
+    # region): the spread of the headline figure.
     s32.propagate(args.warmup)
-    prof = s32.profile_propagate(max(2, args.profile_steps))  # a steady first-axis pass needs 2 steps
-    share = {"axis0": 1, "edge": 1, "mid_fwd": nslab, "last": nslab, "mid_inv": nslab}
-    steady = {k: v for k, v in prof.items() if k in (("axis0",) if nslab > 1 else ("axis0", "mid_fwd", "last", "mid_inv"))}
-    kind = max(steady, key=lambda k: steady[k][1])
-    count, total_ms = steady[kind]
-    avg_ms = total_ms / count
-    launch_bytes = alg_bytes // share[kind]
-    achieved = launch_bytes / (avg_ms / 1e3) / 1e9
-    # The timed region again, five more times, continuing the same solution:
-    # the spread of the headline figure.  (After the roofline steps, so that
-    # those run in the conditions of the timed region; before the pass
-    # timing, which leaves the state overflowed: steps over such data ran
-    # ~5 % faster.)
     reps = []
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -563,61 +675,37 @@ def main() -> int:
         reps.append(ev0.elapsed_time(ev1) / args.steps)
     out["repeats"] = {"ms_per_step": [round(x, 4) for x in reps], "median_ms_per_step": round(float(np.median(reps)), 4),
                       "steps_each": args.steps}
-    # Each back-to-back timing starts from the current solution: repeated
-    # unnormalised transforms grow the values until they overflow, and
-    # passes over such data run faster than over a real state.
-    fresh = s32.buffer.clone()
-
-    def time_fresh(k):
-        s32.buffer.copy_(fresh)
-        return s32.time_pass(k, args.pass_reps)
-
-    timed = {k: min(time_fresh(k) for _ in range(3)) for k in ("axis0", "mid_fwd", "last", "mid_inv")}
-    del fresh
-    lg = int(np.log2(args.n))
-    variant = {"axis0": S.tune_get(False, "c64", lg, True, "potential"),
-               "mid_fwd": S.tune_get(False, "c64", lg, True, "fft"),
-               "mid_inv": S.tune_get(False, "c64", lg, True, "fft"),
-               "last": S.tune_get(False, "c64", lg, False, "kinetic")}
-    traffic = traffic_for(kind, workload, variant[kind]) if share[kind] == 1 else None
-    out["roofline"] = {"bound": "hbm", "kernel": f"pass:{kind}", "achieved": round(achieved, 1),
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": traffic, "variant": variant[kind], "avg_launch_ms": round(avg_ms, 4),
-                       "launches": count, "alg_bytes_per_launch": launch_bytes, "slabs": nslab,
-                       "timing": "in-step, dispatch-attached events",
-                       "passes_in_step": {k: {"launches": c, "avg_ms": round(m / c, 4),
-                                              "GB/s": round(alg_bytes / share.get(k, 1) / (m / c / 1e3) / 1e9, 1)
-                                              if k in share else None}
-                                          for k, (c, m) in prof.items()},
-                       "passes_back_to_back": {k: {"avg_ms": round(m, 4),
-                                                   "GB/s": round(alg_bytes / (m / 1e3) / 1e9, 1)}
-                                               for k, m in timed.items()},
-                       "back_to_back_reps": args.pass_reps}
+    out["roofline"] = roofline_of(S, s32, "c64", prob, workload, args.warmup, args.profile_steps, args.pass_reps)
     # Whole-step view against the 4-pass byte model (64 B per site-step), and
     # against the compulsory floor of one read and one write per step (16 B):
     # the slabs keep part of the middle passes' traffic in the memory-side
     # cache, so the passes move less than 4 x 16 B through HBM.
+    alg_bytes = 2 * sites * BYTES_PER_POINT["c64"]
     step_gbs = 4 * alg_bytes * args.steps / (ms32 / 1e3) / 1e9
     out["step_roofline"] = {"model": "4 passes x (read+write) per step", "achieved": round(step_gbs, 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                             "floor_16B_frac": round(step_gbs / 4 / HBM_PEAK_GBS, 4)}
     s32.close()
     torch.cuda.synchronize()
+    # What a plain streaming copy reaches on this machine, beside the 8 TB/s peak.
+    out["hbm_copy"] = copy_bandwidth()
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / out["hbm_copy"]["GB/s"], 4)
     if not args.no_fp64:
-        # Same start, same number of steps, FP64 state: the FP32 error of this run.
+        # Same start, same number of steps, FP64 state: the FP32 error of the
+        # timed run; then the FP64 dominant kernel's roofline.
         s64, ms64, _, tuned64 = time_gpu(S, prob, "c128", args.steps, args.warmup, tune_reps)
         b = s64.get_state("c128")
 
         def err(psi32):
             return float(np.linalg.norm(psi32.astype(np.complex128) - b) / np.linalg.norm(b))
 
-        rel, drift = err(state32), drift32
         out["fp64"] = {"value": sites * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                        "dtype": "f64"}
         if tuned64:
             out["fp64"]["autotune_chosen"] = {c: min(row, key=row.get) for c, row in tuned64.items()}
-        out["accuracy"] = {"steps": args.warmup + args.steps, "rel_l2_f32_vs_f64": rel,
-                           "norm_drift_f32": drift, "norm_drift_f64": abs(s64.observables(1)["norm"] - 1.0)}
+        out["accuracy_timed_run"] = {"steps": args.warmup + args.steps, "rel_l2_f32_vs_f64": err(state32),
+                                     "norm_drift_f32": drift32,
+                                     "norm_drift_f64": abs(s64.observables(1)["norm"] - 1.0)}
         if args.also_c64x:
             sx, msx, _, _ = time_gpu(S, prob, "c64x", args.steps, args.warmup)
             relx, driftx = err(sx.get_state("c64")), abs(sx.observables(1)["norm"] - 1.0)
@@ -625,8 +713,14 @@ def main() -> int:
                            "dtype": "f64 arithmetic, f32 state", "rel_l2_vs_f64": relx, "norm_drift": driftx,
                            "passes": {k: round(m / c, 4) for k, (c, m) in sx.profile_propagate(4).items()}}
             sx.close()
-        s64.close()
         del state32, b
+        out["fp64"]["roofline"] = roofline_of(S, s64, "c128", prob, workload, args.warmup, args.profile_steps,
+                                              args.pass_reps)
+        out["fp64"]["roofline"]["frac_of_copy"] = round(out["fp64"]["roofline"]["achieved"] / out["hbm_copy"]["GB/s"], 4)
+        s64.close()
+        torch.cuda.synchronize()
+        if args.accuracy_steps > 0:
+            out["accuracy"] = full_length_accuracy(S, W, args.n, args.accuracy_steps)
 
     if not args.no_batch:
         out["batch"] = batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200,
@@ -637,7 +731,7 @@ def main() -> int:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         out["serving"] = serve_bench(S, W, V, args.serve_requests, args.serve_warmup, rates,
                                      args.serve_capacity_requests, args.serve_tick, args.serve_graph_steps,
-                                     args.serve_budget_gib, 20)
+                                     args.serve_budget_gib, 20, args.serve_seconds)
     if args.small_workloads:
         out["small_workloads"] = small_workloads(S, W, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
