@@ -512,13 +512,19 @@ def rocprof_summary(base: str, n: int, precision: str = "all") -> int:
         return per
 
     sq, fe, wr = counters("sq"), counters("fetch"), counters("write")
+    # Every 1 GiB device copy of the run (the --copy-calibration ones and the
+    # copy-bandwidth timing); the median reading, since a dispatch now and
+    # then reports the counts of two.
     copy = next(k for k in fe if k[0] == "__amd_rocclr_copyBuffer")
     kib = (1 << 30) / 1024
-    sf = kib / max(fe[copy]["FETCH_SIZE"])
-    sw = kib / max(wr[copy]["WRITE_SIZE"])
-    print(f"Counter calibration (1 GiB device copy: 1 GiB read, 1 GiB written): FETCH_SIZE reads "
-          f"{max(fe[copy]['FETCH_SIZE']):.0f} KiB -> scale {sf:.4f}; WRITE_SIZE reads "
-          f"{max(wr[copy]['WRITE_SIZE']):.0f} KiB -> scale {sw:.4f}.")
+    med = lambda xs: float(np.median(xs))
+    sf = kib / med(fe[copy]["FETCH_SIZE"])
+    sw = kib / med(wr[copy]["WRITE_SIZE"])
+    print(f"Counter calibration (1 GiB device copies: 1 GiB read, 1 GiB written each): FETCH_SIZE reads "
+          f"{med(fe[copy]['FETCH_SIZE']):.0f} KiB (median of {len(fe[copy]['FETCH_SIZE'])} copies; "
+          f"{min(fe[copy]['FETCH_SIZE']):.0f}..{max(fe[copy]['FETCH_SIZE']):.0f}) -> scale {sf:.4f}; WRITE_SIZE reads "
+          f"{med(wr[copy]['WRITE_SIZE']):.0f} KiB ({min(wr[copy]['WRITE_SIZE']):.0f}..{max(wr[copy]['WRITE_SIZE']):.0f}) "
+          f"-> scale {sw:.4f}.")
     print()
     print("| kernel | part of grid | launches | avg µs | in-step launches | in-step avg µs | back-to-back avg µs "
           "| HBM read GB/launch | HBM write GB/launch | GB/s | LDS conflict cycles / LDS instr | VALU instr / wave |")
