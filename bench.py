@@ -421,6 +421,37 @@ def small_workloads(S, W, with_oracle: bool):
     return out
 
 
+def mixed_radix(S, W, sizes, steps: int = 20, warmup: int = 5):
+    """The 3D soft-core workload at the same spacing (0.15625) on grids whose
+    lengths are 7-smooth but not powers of two (the sizes the paper advises
+    for the transforms): site-steps/s in FP32 and FP64 state, one step being
+    the same four-pass schedule run by the mixed-radix kernels (FP64
+    arithmetic in both)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    out = {}
+    for n in sizes:
+        row = {}
+        for prec in ("c64", "c128"):
+            prob = W.softcore_3d(n=n, precision=prec, half_width=n * 0.078125)
+            s = S.from_problem(prob, stream=stream)
+            s.propagate(warmup)
+            s.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.propagate(steps)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            s.close()
+            row[prec] = {"ms_per_step": round(ms, 4), "site_steps_per_s": n ** 3 / (ms / 1e3),
+                         "bytes_frac_of_hbm_peak_4pass": round(4 * 2 * BYTES_PER_POINT[prec] * n ** 3 /
+                                                               (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        out[f"{n}^3"] = row
+    return out
+
+
 def rocprof_summary(base: str, n: int, precision: str = "all") -> int:
     """Summarise the four rocprofv3 runs of this benchmark (kernel trace,
     SQ counters, FETCH_SIZE, WRITE_SIZE, written with -d base/<name> -o
@@ -612,6 +643,8 @@ def main() -> int:
     ap.add_argument("--serve-budget-gib", type=float, default=192.0)
     ap.add_argument("--small-workloads", action="store_true",
                     help="also time the 1D (1024 points) and 2D (1024^2) workloads and their oracle")
+    ap.add_argument("--mixed-radix", type=str, default="",
+                    help="comma-separated 7-smooth axis lengths: also time the 3D workload on those cubes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--summary-precision", choices=("all", "c64", "c128"), default="all",
@@ -740,6 +773,8 @@ def main() -> int:
                                      args.serve_budget_gib, 20, args.serve_seconds)
     if args.small_workloads:
         out["small_workloads"] = small_workloads(S, W, not args.no_cpu_baseline)
+    if args.mixed_radix:
+        out["mixed_radix"] = mixed_radix(S, W, [int(x) for x in args.mixed_radix.split(",") if x])
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["oracle_parity"] = cpu_baseline(S, W.softcore_3d(n=args.n, precision="c128"),
                                                                  args.cpu_seconds)

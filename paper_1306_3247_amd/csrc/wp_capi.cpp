@@ -435,7 +435,7 @@ hipError_t launch_any(const wp_sim *s, const wp::PassArgs &a, hipStream_t st) {
   for (int d = a.axis + 1; d < 3; ++d) ga.inner *= (int64_t)s->g.n[d];
   ga.p.n_lines = s->total / (int64_t)s->g.n[a.axis];
   ga.plan = s->plan[a.axis];
-  return wp::launch_gpass(s->prec == WP_C128 ? 2 : 1, ga, st);
+  return wp::launch_gpass(s->prec, ga, st);
 }
 
 void use_half_kinetic(const wp_sim *s, wp::PassArgs &a) {

@@ -8,8 +8,18 @@
 // exp(-+2 pi i r (j mod LS)/(R LS)), does an R-point DFT and writes output q
 // to (j - j mod LS) R + (j mod LS) + q LS, alternating between two LDS
 // buffers), applies the same phase factors as the power-of-two passes, and
-// stores the lines back.  All arithmetic is FP64 whatever the storage type.
-// Grid indices come from divisions by the runtime lengths.
+// stores the lines back.  All arithmetic is FP64; the line passes keep the
+// values between stages in LDS as FP32 for an FP32 state (one rounding per
+// stage, as the power-of-two FP32 passes round every addition) and as FP64
+// otherwise.
+//
+// Line passes: the tile (T lines, a power of two chosen on the host so that
+// two workgroups fit in a CU's LDS) sits in LDS point-major, element
+// (j, line tau) at j (T + 1) + tau, so that neighbouring lanes take
+// neighbouring lines when loading a strided axis and neighbouring points
+// when loading the contiguous one; the storage offset of each line and its
+// phase or kinetic constants (the terms of the other axes) are computed once
+// per tile.
 #include "wp_pass.hpp"
 
 namespace wp {
@@ -121,120 +131,244 @@ __device__ cx<double> *gfft(cx<double> *a, cx<double> *b, int N, int tile, const
   return a;
 }
 
-// Multi-index of element j of line `line` along `axis`.
-__device__ __forceinline__ void line_point(const GridDev &g, int axis, int64_t inner, int64_t line, int j,
-                                           int idx[3]) {
-  int64_t c = line % inner, o = line / inner;
-#pragma unroll
-  for (int d = 2; d >= 0; --d) {
-    if (d > axis) {
-      idx[d] = (int)(c % g.n[d]);
-      c /= g.n[d];
-    }
+// ---- line passes -----------------------------------------------------------
+constexpr int kLThreads = 512;
+
+// Tile of a line pass: T lines (T = 2^lgT), TP = T + 1 (T > 1) entries per
+// point in LDS.
+struct LTile {
+  int32_t T, lgT, TP;
+};
+
+// q = x / d and r = x mod d for 0 <= x, d < 2^16, from an FP32 estimate
+// corrected by one step (inv = 1/d rounded to FP32).
+__device__ __forceinline__ int divmod16(int x, int d, float inv, int &r) {
+  int q = (int)((float)x * inv);
+  r = x - q * d;
+  if (r < 0) {
+    --q;
+    r += d;
+  } else if (r >= d) {
+    ++q;
+    r -= d;
   }
-#pragma unroll
-  for (int d = 2; d >= 0; --d) {
-    if (d < axis) {
-      idx[d] = (int)(o % g.n[d]);
-      o /= g.n[d];
-    }
-  }
-  idx[axis] = j;
+  return q;
 }
 
-// Phase of the potential at a grid point: vtau * V(x, t), V from the
-// waveform values `cf` (the same form as the power-of-two passes).
-__device__ __forceinline__ double potential_phase(const PassArgs &a, const double *cf, const int idx[3]) {
-  double xs[3] = {0.0, 0.0, 0.0};
-  double v = cf[CO_C];
-  for (int d = 0; d < a.g.ndim; ++d) {
-    xs[d] = a.g.lo[d] + (double)idx[d] * a.g.dx[d];
-    v += cf[CO_A + d] * xs[d] + cf[CO_B + d] * xs[d] * xs[d];
-  }
-  if (a.pot.v0_kind != 0) v += cf[CO_S] * v0_value(a.pot, xs[0], xs[1], xs[2], a.g.ndim);
-  return a.vtau * v;
-}
-
-template <class S>
-__device__ __forceinline__ void gpass_body(const GPassArgs &ga, int kind) {
-  using T = typename storage<S>::type;
-  __shared__ cx<double> s_buf[2 * kGBuf];
-  const PassArgs &a = ga.p;
-  const int N = a.g.n[a.axis];
-  const int tile = kGBuf / N < 16 ? kGBuf / N : 16;
-  const int64_t inner = ga.inner;
-  const bool strided = inner > 1;
-  const int64_t line0 = (int64_t)blockIdx.x * tile;
-  T *psi = (T *)a.psi;
-  const uint32_t ops = a.ops;
-  auto addr = [&](int64_t line, int j) -> int64_t {
-    return (line / inner) * N * inner + line % inner + (int64_t)j * inner;
-  };
-  // Strided lines: consecutive threads take neighbouring lines (contiguous in
-  // memory); contiguous lines: consecutive points of one line.
-  auto which = [&](int e, int &tau, int &j) {
-    if (strided) {
-      tau = e % tile;
-      j = e / tile;
-    } else {
-      tau = e / N;
-      j = e - tau * N;
-    }
-  };
-  cx<double> *A = s_buf;
-  for (int e = threadIdx.x; e < tile * N; e += kGThreads) {
-    int tau, j;
-    which(e, tau, j);
-    const int64_t line = line0 + tau;
-    A[tau * N + j] = line < a.n_lines ? load_as<double>(psi + addr(line, j)) : cx<double>{0.0, 0.0};
-  }
-  __syncthreads();
-  auto other = [&](cx<double> *p) { return p == s_buf ? s_buf + kGBuf : s_buf; };
-  if (kind == PK_F) {
-    A = (ops & OP_PRE_INV) ? gfft<true>(A, other(A), N, tile, ga.plan, a.tw)
-                           : gfft<false>(A, other(A), N, tile, ga.plan, a.tw);
-  } else if (kind == PK_K) {
-    A = gfft<false>(A, other(A), N, tile, ga.plan, a.tw);
-    for (int e = threadIdx.x; e < tile * N; e += kGThreads) {
-      int tau, j;
-      which(e, tau, j);
-      const int64_t line = line0 + tau;
-      if (line >= a.n_lines) continue;
-      int idx[3];
-      line_point(a.g, a.axis, inner, line, j, idx);
-      cx<double> f = {1.0, 0.0};
-      for (int d = 0; d < a.g.ndim; ++d) f = cmul(f, a.ktab[d][idx[d]]);
-      A[tau * N + j] = cmul(A[tau * N + j], f);
+// One transform of the tile, stage by stage from buffer `a` into `b` and
+// back; returns the buffer holding the result.  Every thread calls it.
+template <bool INV, class E>
+__device__ E *lfft(E *a, E *b, int N, const LTile &t, const GPlan &plan, const cx<double> *tw) {
+  for (int s = 0; s < plan.nst; ++s) {
+    const int R = plan.radix[s], LS = plan.ls[s];
+    const int nb = N / R;
+    const float inv_ls = 1.0f / (float)LS;
+    const cx<double> *tws = tw + plan.twoff[s];
+    for (int e = threadIdx.x; e < (nb << t.lgT); e += kLThreads) {
+      const int tau = e & (t.T - 1), jb = e >> t.lgT;
+      int k;
+      (void)divmod16(jb, LS, inv_ls, k);
+      cx<double> x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        if (r < R) {
+          const E *p = a + 2 * ((jb + r * nb) * t.TP + tau);
+          x[r] = {(double)p[0], (double)p[1]};
+        }
+      if (LS > 1) {
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+          if (r < R) {
+            cx<double> w = tws[(r - 1) * LS + k];
+            if (INV) w.y = -w.y;
+            x[r] = cmul(x[r], w);
+          }
+        }
+      }
+      dft_any<INV>(x, R);
+      const int o0 = (jb - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < R) {
+          E *p = b + 2 * ((o0 + q * LS) * t.TP + tau);
+          p[0] = (E)x[q].x;
+          p[1] = (E)x[q].y;
+        }
     }
     __syncthreads();
-    A = gfft<true>(A, other(A), N, tile, ga.plan, a.tw);
+    E *tmp = a;
+    a = b;
+    b = tmp;
+  }
+  return a;
+}
+
+// Line pass of a mixed-length grid: kind PK_F (one transform), PK_K
+// (transform, kinetic factor, inverse), PK_V ([inverse] potential phase
+// [transform]), with the tile in dynamic LDS: two buffers of N (T + 1)
+// complex E, then per line its storage offset and constants.
+template <class S, class E, int KIND>
+__global__ void __launch_bounds__(kLThreads) lpass_kernel(GPassArgs ga, LTile t) {
+  using T = typename storage<S>::type;
+  extern __shared__ __align__(16) unsigned char l_lds[];
+  const PassArgs &a = ga.p;
+  const int N = a.g.n[a.axis];
+  const int64_t inner = ga.inner;
+  const int tid = threadIdx.x;
+  E *const buf0 = reinterpret_cast<E *>(l_lds), *const buf1 = buf0 + 2 * N * t.TP;
+  auto other = [&](E *p) { return p == buf0 ? buf1 : buf0; };
+  E *A = buf0;
+  int64_t *lbase = reinterpret_cast<int64_t *>(buf1 + 2 * N * t.TP);  // T storage offsets (-1: no line)
+  double *lc = reinterpret_cast<double *>(lbase + t.T);              // T x 4 constants
+  const int64_t line0 = (int64_t)blockIdx.x << t.lgT;
+  const uint32_t ops = a.ops;
+  const int ax = a.axis;
+
+  // Per line: storage offset of its first point, and the constants of the
+  // other axes (potential: phase and r^2 terms; kinetic: factor product).
+  if (tid < t.T) {
+    const int64_t line = line0 + tid;
+    double c0 = 0.0, c1 = 0.0, c2 = 1.0, c3 = 0.0;
+    if (line < a.n_lines) {
+      const int64_t o = line / inner, c = line - o * inner;
+      lbase[tid] = o * (int64_t)N * inner + c;
+      int idx[3] = {0, 0, 0};
+      int64_t cc = c, oo = o;
+#pragma unroll
+      for (int d = 2; d >= 0; --d) {
+        if (d > ax) {
+          idx[d] = (int)(cc % a.g.n[d]);
+          cc /= a.g.n[d];
+        }
+      }
+#pragma unroll
+      for (int d = 2; d >= 0; --d) {
+        if (d < ax) {
+          idx[d] = (int)(oo % a.g.n[d]);
+          oo /= a.g.n[d];
+        }
+      }
+      if (KIND == PK_V) {
+        const double *cf = a.coef;
+        double th = cf[CO_C], rho2 = 0.0;
+        for (int d = 0; d < a.g.ndim; ++d) {
+          if (d == ax) continue;
+          const double x = a.g.lo[d] + (double)idx[d] * a.g.dx[d];
+          th += cf[CO_A + d] * x + cf[CO_B + d] * x * x;
+          rho2 += x * x;
+        }
+        c0 = th * a.vtau;
+        c1 = rho2;
+      } else if (KIND == PK_K) {
+        cx<double> f = {1.0, 0.0};
+        for (int d = 0; d < a.g.ndim; ++d)
+          if (d != ax) f = cmul(f, a.ktab[d][idx[d]]);
+        c2 = f.x;
+        c3 = f.y;
+      }
+    } else {
+      lbase[tid] = -1;
+    }
+    lc[4 * tid + 0] = c0;
+    lc[4 * tid + 1] = c1;
+    lc[4 * tid + 2] = c2;
+    lc[4 * tid + 3] = c3;
+  }
+  __syncthreads();
+
+  // Load: strided axes with neighbouring lanes on neighbouring lines (one
+  // row segment per T lanes), the contiguous axis line by line.
+  T *psi = (T *)a.psi;
+  if (inner > 1) {
+    for (int e = tid; e < (N << t.lgT); e += kLThreads) {
+      const int tau = e & (t.T - 1), j = e >> t.lgT;
+      const int64_t b = lbase[tau];
+      const cx<double> v = b >= 0 ? load_as<double>(psi + b + (int64_t)j * inner) : cx<double>{0.0, 0.0};
+      E *p = A + 2 * (j * t.TP + tau);
+      p[0] = (E)v.x;
+      p[1] = (E)v.y;
+    }
   } else {
-    if (ops & OP_PRE_INV) A = gfft<true>(A, other(A), N, tile, ga.plan, a.tw);
+    for (int tau = 0; tau < t.T; ++tau) {
+      const int64_t b = lbase[tau];
+      for (int j = tid; j < N; j += kLThreads) {
+        const cx<double> v = b >= 0 ? load_as<double>(psi + b + j) : cx<double>{0.0, 0.0};
+        E *p = A + 2 * (j * t.TP + tau);
+        p[0] = (E)v.x;
+        p[1] = (E)v.y;
+      }
+    }
+  }
+  __syncthreads();
+
+  if constexpr (KIND == PK_F) {
+    A = (ops & OP_PRE_INV) ? lfft<true>(A, other(A), N, t, ga.plan, a.tw)
+                           : lfft<false>(A, other(A), N, t, ga.plan, a.tw);
+  } else if constexpr (KIND == PK_K) {
+    A = lfft<false>(A, other(A), N, t, ga.plan, a.tw);
+    const cx<double> *kt = a.ktab[ax];
+    for (int e = tid; e < (N << t.lgT); e += kLThreads) {
+      const int tau = e & (t.T - 1), j = e >> t.lgT;
+      const cx<double> f = cmul(kt[j], cx<double>{lc[4 * tau + 2], lc[4 * tau + 3]});
+      E *p = A + 2 * (j * t.TP + tau);
+      const cx<double> v = cmul(cx<double>{(double)p[0], (double)p[1]}, f);
+      p[0] = (E)v.x;
+      p[1] = (E)v.y;
+    }
+    __syncthreads();
+    A = lfft<true>(A, other(A), N, t, ga.plan, a.tw);
+  } else {
+    if (ops & OP_PRE_INV) A = lfft<true>(A, other(A), N, t, ga.plan, a.tw);
     if (ops & OP_V) {
-      for (int e = threadIdx.x; e < tile * N; e += kGThreads) {
-        int tau, j;
-        which(e, tau, j);
-        const int64_t line = line0 + tau;
-        if (line >= a.n_lines) continue;
-        int idx[3];
-        line_point(a.g, a.axis, inner, line, j, idx);
-        A[tau * N + j] = cmul(A[tau * N + j], expmi_wave(potential_phase(a, a.coef, idx)));
+      const double *cf = a.coef;
+      const double vt = a.vtau;
+      const double ca = vt * cf[CO_A + ax], cb = vt * cf[CO_B + ax], cs = vt * cf[CO_S];
+      const int vk = a.pot.v0_kind;
+      const double p0 = a.pot.v0_par[0], p1 = a.pot.v0_par[1], p2 = a.pot.v0_par[2];
+      const double lo = a.g.lo[ax], dx = a.g.dx[ax];
+      for (int e = tid; e < (N << t.lgT); e += kLThreads) {
+        const int tau = e & (t.T - 1), j = e >> t.lgT;
+        const double x = lo + (double)j * dx;
+        double th = lc[4 * tau + 0] + x * fma(cb, x, ca);
+        if (vk == 1) {
+          th -= cs * p0 * rsqrt_fast(fma(x, x, lc[4 * tau + 1] + p1));
+        } else if (vk == 2) {
+          const double m = 1.0 - exp(-p1 * (x - p2));
+          th += cs * p0 * m * m;
+        }
+        E *p = A + 2 * (j * t.TP + tau);
+        const cx<double> v = cmul(cx<double>{(double)p[0], (double)p[1]}, expmi_wave(th));
+        p[0] = (E)v.x;
+        p[1] = (E)v.y;
       }
       __syncthreads();
     }
-    if (ops & OP_FWD) A = gfft<false>(A, other(A), N, tile, ga.plan, a.tw);
+    if (ops & OP_FWD) A = lfft<false>(A, other(A), N, t, ga.plan, a.tw);
   }
-  for (int e = threadIdx.x; e < tile * N; e += kGThreads) {
-    int tau, j;
-    which(e, tau, j);
-    const int64_t line = line0 + tau;
-    if (line < a.n_lines) store_from(psi + addr(line, j), A[tau * N + j]);
+
+  if (inner > 1) {
+    for (int e = tid; e < (N << t.lgT); e += kLThreads) {
+      const int tau = e & (t.T - 1), j = e >> t.lgT;
+      const int64_t b = lbase[tau];
+      const E *p = A + 2 * (j * t.TP + tau);
+      if (b >= 0) store_from(psi + b + (int64_t)j * inner, cx<double>{(double)p[0], (double)p[1]});
+    }
+  } else {
+    for (int tau = 0; tau < t.T; ++tau) {
+      const int64_t b = lbase[tau];
+      if (b < 0) continue;
+      for (int j = tid; j < N; j += kLThreads) {
+        const E *p = A + 2 * (j * t.TP + tau);
+        store_from(psi + b + j, cx<double>{(double)p[0], (double)p[1]});
+      }
+    }
   }
 }
 
-template <class S, int KIND>
-__global__ void __launch_bounds__(kGThreads) gpass_kernel(GPassArgs ga) {
-  gpass_body<S>(ga, KIND);
+// LDS bytes of a tile of T lines of N points.
+__host__ inline size_t ltile_bytes(int N, int T, int esize) {
+  const int TP = T > 1 ? T + 1 : 1;
+  return (size_t)2 * N * TP * 2 * esize + (size_t)T * (8 + 32);
 }
 
 // The whole 1D solve in one workgroup, as the power-of-two solver: merged
@@ -293,20 +427,46 @@ __global__ void __launch_bounds__(kGThreads) gsolve1d_kernel(Solve1DArgs a, GPla
 hipError_t launch_gpass(int prec, const GPassArgs &ga, hipStream_t s) {
   const int N = ga.p.g.n[ga.p.axis];
   if (N < 2 || N > kMaxMixed || ga.plan.nst < 1 || ga.plan.nst > kMaxStages) return hipErrorInvalidValue;
-  const int tile = kGBuf / N < 16 ? kGBuf / N : 16;
-  const int64_t blocks = (ga.p.n_lines + tile - 1) / tile;
-  if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const uint32_t ops = ga.p.ops;
   const int kind = (ops & OP_V) ? PK_V : (ops & OP_K) ? PK_K : PK_F;
-  const dim3 g((unsigned)blocks), b(kGThreads);
+  // LDS element: FP32 for an FP32 state with FP32 arithmetic (prec 1), FP64
+  // for the FP64 state (2) and for the FP32 state with FP64 arithmetic (3).
+  const int esize = prec == 1 ? 4 : 8;
+  // Lines per tile: up to 16 (FP32 storage) or 8 (FP64) neighbouring lines,
+  // so that a strided row segment is up to 128 bytes; no more than LDS for
+  // two workgroups per CU allows (one for the longest lines).
+  int T = prec == 2 ? 8 : 16;
+  while (T > 1 && (ltile_bytes(N, T, esize) > 80 * 1024 || T > ga.p.n_lines)) T >>= 1;
+  const size_t shm = ltile_bytes(N, T, esize);
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  LTile t{T, __builtin_ctz((unsigned)T), T > 1 ? T + 1 : 1};
+  const int64_t blocks = (ga.p.n_lines + T - 1) / T;
+  if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 g((unsigned)blocks), b(kLThreads);
+  auto go = [&](auto kernel) -> hipError_t {
+    // Dynamic LDS beyond the default limit needs the attribute once per kernel.
+    static bool ready = false;
+    if (!ready) {
+      hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         160 * 1024);
+      if (e != hipSuccess) return e;
+      ready = true;
+    }
+    return launch_kernel_shm(kernel, g, b, shm, s, ga, t);
+  };
   if (prec == 2) {
-    if (kind == PK_V) return launch_kernel(gpass_kernel<double, PK_V>, g, b, s, ga);
-    if (kind == PK_K) return launch_kernel(gpass_kernel<double, PK_K>, g, b, s, ga);
-    return launch_kernel(gpass_kernel<double, PK_F>, g, b, s, ga);
+    if (kind == PK_V) return go(lpass_kernel<double, double, PK_V>);
+    if (kind == PK_K) return go(lpass_kernel<double, double, PK_K>);
+    return go(lpass_kernel<double, double, PK_F>);
   }
-  if (kind == PK_V) return launch_kernel(gpass_kernel<float, PK_V>, g, b, s, ga);
-  if (kind == PK_K) return launch_kernel(gpass_kernel<float, PK_K>, g, b, s, ga);
-  return launch_kernel(gpass_kernel<float, PK_F>, g, b, s, ga);
+  if (prec == 3) {
+    if (kind == PK_V) return go(lpass_kernel<float, double, PK_V>);
+    if (kind == PK_K) return go(lpass_kernel<float, double, PK_K>);
+    return go(lpass_kernel<float, double, PK_F>);
+  }
+  if (kind == PK_V) return go(lpass_kernel<float, float, PK_V>);
+  if (kind == PK_K) return go(lpass_kernel<float, float, PK_K>);
+  return go(lpass_kernel<float, float, PK_F>);
 }
 
 hipError_t launch_gsolve1d(int prec, const Solve1DArgs &a, const GPlan &plan, hipStream_t s) {

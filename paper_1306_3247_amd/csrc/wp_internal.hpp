@@ -190,9 +190,24 @@ inline hipError_t launch_kernel(K kernel, dim3 grid, dim3 block, hipStream_t s, 
   return hipGetLastError();
 }
 
+// The same with `shm` bytes of dynamic LDS.
+template <class K, class... A>
+inline hipError_t launch_kernel_shm(K kernel, dim3 grid, dim3 block, size_t shm, hipStream_t s, A... args) {
+  DispatchEvents &d = tl_dispatch_events;
+  if (d.start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, d.start, d.stop, 0, args...);
+    d.used = true;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+  }
+  return hipGetLastError();
+}
+
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_pass(int prec, const PassArgs &a, hipStream_t s);
 hipError_t launch_solve1d(int prec, const Solve1DArgs &a, hipStream_t s);
+// Mixed-radix line pass; prec is the handle's wp_precision (1 FP32, 2 FP64,
+// 3 FP32 state with FP64 arithmetic).
 hipError_t launch_gpass(int prec, const GPassArgs &a, hipStream_t s);
 // 1D solve of any supported mixed length in one workgroup (a.g.n[0] points).
 hipError_t launch_gsolve1d(int prec, const Solve1DArgs &a, const GPlan &plan, hipStream_t s);
