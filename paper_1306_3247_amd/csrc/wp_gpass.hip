@@ -133,6 +133,9 @@ __device__ cx<double> *gfft(cx<double> *a, cx<double> *b, int N, int tile, const
 
 // ---- line passes -----------------------------------------------------------
 constexpr int kLThreads = 512;
+// Points of a tile per thread at most (the host caps T N at this times
+// kLThreads).
+constexpr int kLMaxPer = 16;
 
 // Tile of a line pass: T lines (T = 2^lgT), TP = T + 1 (T > 1) entries per
 // point in LDS.
@@ -155,45 +158,55 @@ __device__ __forceinline__ int divmod16(int x, int d, float inv, int &r) {
   return q;
 }
 
+// One stage of radix R of the tile's transform, from buffer `a` into `b`.
+template <bool INV, int R, class E>
+__device__ __forceinline__ void lstage(const E *a, E *b, int N, int LS, const cx<double> *tws, const LTile &t) {
+  const int nb = N / R;
+  const float inv_ls = 1.0f / (float)LS;
+  for (int e = threadIdx.x; e < (nb << t.lgT); e += kLThreads) {
+    const int tau = e & (t.T - 1), jb = e >> t.lgT;
+    int k;
+    (void)divmod16(jb, LS, inv_ls, k);
+    cx<double> x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const E *p = a + 2 * ((jb + r * nb) * t.TP + tau);
+      x[r] = {(double)p[0], (double)p[1]};
+    }
+    if (LS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<double> w = tws[(r - 1) * LS + k];
+        if (INV) w.y = -w.y;
+        x[r] = cmul(x[r], w);
+      }
+    }
+    if constexpr (R == 3 || R == 5 || R == 7) dft_odd<R, INV>(x);
+    else dft<R, INV>(x);
+    const int o0 = (jb - k) * R + k;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      E *p = b + 2 * ((o0 + q * LS) * t.TP + tau);
+      p[0] = (E)x[q].x;
+      p[1] = (E)x[q].y;
+    }
+  }
+}
+
 // One transform of the tile, stage by stage from buffer `a` into `b` and
 // back; returns the buffer holding the result.  Every thread calls it.
 template <bool INV, class E>
 __device__ E *lfft(E *a, E *b, int N, const LTile &t, const GPlan &plan, const cx<double> *tw) {
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.radix[s], LS = plan.ls[s];
-    const int nb = N / R;
-    const float inv_ls = 1.0f / (float)LS;
     const cx<double> *tws = tw + plan.twoff[s];
-    for (int e = threadIdx.x; e < (nb << t.lgT); e += kLThreads) {
-      const int tau = e & (t.T - 1), jb = e >> t.lgT;
-      int k;
-      (void)divmod16(jb, LS, inv_ls, k);
-      cx<double> x[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < R) {
-          const E *p = a + 2 * ((jb + r * nb) * t.TP + tau);
-          x[r] = {(double)p[0], (double)p[1]};
-        }
-      if (LS > 1) {
-#pragma unroll
-        for (int r = 1; r < 8; ++r) {
-          if (r < R) {
-            cx<double> w = tws[(r - 1) * LS + k];
-            if (INV) w.y = -w.y;
-            x[r] = cmul(x[r], w);
-          }
-        }
-      }
-      dft_any<INV>(x, R);
-      const int o0 = (jb - k) * R + k;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < R) {
-          E *p = b + 2 * ((o0 + q * LS) * t.TP + tau);
-          p[0] = (E)x[q].x;
-          p[1] = (E)x[q].y;
-        }
+    switch (R) {
+      case 2: lstage<INV, 2>(a, b, N, LS, tws, t); break;
+      case 3: lstage<INV, 3>(a, b, N, LS, tws, t); break;
+      case 4: lstage<INV, 4>(a, b, N, LS, tws, t); break;
+      case 5: lstage<INV, 5>(a, b, N, LS, tws, t); break;
+      case 7: lstage<INV, 7>(a, b, N, LS, tws, t); break;
+      default: lstage<INV, 8>(a, b, N, LS, tws, t); break;
     }
     __syncthreads();
     E *tmp = a;
@@ -276,26 +289,44 @@ __global__ void __launch_bounds__(kLThreads) lpass_kernel(GPassArgs ga, LTile t)
   }
   __syncthreads();
 
-  // Load: strided axes with neighbouring lanes on neighbouring lines (one
-  // row segment per T lanes), the contiguous axis line by line.
+  // Load: element e of the tile (e < N T, at most kLMaxPer per thread) is
+  // point e >> lgT of line e & (T-1) on strided axes (neighbouring lanes on
+  // neighbouring lines: one row segment per T lanes), and point e mod N of
+  // line e / N on the contiguous axis.  Every load of a thread is issued
+  // before the first is waited for.
   T *psi = (T *)a.psi;
-  if (inner > 1) {
-    for (int e = tid; e < (N << t.lgT); e += kLThreads) {
-      const int tau = e & (t.T - 1), j = e >> t.lgT;
-      const int64_t b = lbase[tau];
-      const cx<double> v = b >= 0 ? load_as<double>(psi + b + (int64_t)j * inner) : cx<double>{0.0, 0.0};
-      E *p = A + 2 * (j * t.TP + tau);
-      p[0] = (E)v.x;
-      p[1] = (E)v.y;
+  const int total = N << t.lgT;
+  const float inv_n = 1.0f / (float)N;
+  auto point = [&](int e, int &tau, int &j) {
+    if (inner > 1) {
+      tau = e & (t.T - 1);
+      j = e >> t.lgT;
+    } else {
+      tau = divmod16(e, N, inv_n, j);
     }
-  } else {
-    for (int tau = 0; tau < t.T; ++tau) {
-      const int64_t b = lbase[tau];
-      for (int j = tid; j < N; j += kLThreads) {
-        const cx<double> v = b >= 0 ? load_as<double>(psi + b + j) : cx<double>{0.0, 0.0};
+  };
+  {
+    cx<double> v[kLMaxPer];
+#pragma unroll
+    for (int i = 0; i < kLMaxPer; ++i) {
+      const int e = tid + i * kLThreads;
+      v[i] = {0.0, 0.0};
+      if (e < total) {
+        int tau, j;
+        point(e, tau, j);
+        const int64_t b = lbase[tau];
+        if (b >= 0) v[i] = load_as<double>(psi + b + (int64_t)j * inner);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kLMaxPer; ++i) {
+      const int e = tid + i * kLThreads;
+      if (e < total) {
+        int tau, j;
+        point(e, tau, j);
         E *p = A + 2 * (j * t.TP + tau);
-        p[0] = (E)v.x;
-        p[1] = (E)v.y;
+        p[0] = (E)v[i].x;
+        p[1] = (E)v[i].y;
       }
     }
   }
@@ -346,21 +377,15 @@ __global__ void __launch_bounds__(kLThreads) lpass_kernel(GPassArgs ga, LTile t)
     if (ops & OP_FWD) A = lfft<false>(A, other(A), N, t, ga.plan, a.tw);
   }
 
-  if (inner > 1) {
-    for (int e = tid; e < (N << t.lgT); e += kLThreads) {
-      const int tau = e & (t.T - 1), j = e >> t.lgT;
+#pragma unroll
+  for (int i = 0; i < kLMaxPer; ++i) {
+    const int e = tid + i * kLThreads;
+    if (e < total) {
+      int tau, j;
+      point(e, tau, j);
       const int64_t b = lbase[tau];
       const E *p = A + 2 * (j * t.TP + tau);
       if (b >= 0) store_from(psi + b + (int64_t)j * inner, cx<double>{(double)p[0], (double)p[1]});
-    }
-  } else {
-    for (int tau = 0; tau < t.T; ++tau) {
-      const int64_t b = lbase[tau];
-      if (b < 0) continue;
-      for (int j = tid; j < N; j += kLThreads) {
-        const E *p = A + 2 * (j * t.TP + tau);
-        store_from(psi + b + j, cx<double>{(double)p[0], (double)p[1]});
-      }
     }
   }
 }
@@ -436,7 +461,7 @@ hipError_t launch_gpass(int prec, const GPassArgs &ga, hipStream_t s) {
   // so that a strided row segment is up to 128 bytes; no more than LDS for
   // two workgroups per CU allows (one for the longest lines).
   int T = prec == 2 ? 8 : 16;
-  while (T > 1 && (ltile_bytes(N, T, esize) > 80 * 1024 || T > ga.p.n_lines)) T >>= 1;
+  while (T > 1 && (ltile_bytes(N, T, esize) > 80 * 1024 || T > ga.p.n_lines || N * T > kLMaxPer * kLThreads)) T >>= 1;
   const size_t shm = ltile_bytes(N, T, esize);
   if (shm > 160 * 1024) return hipErrorInvalidValue;
   LTile t{T, __builtin_ctz((unsigned)T), T > 1 ? T + 1 : 1};
