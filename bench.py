@@ -643,8 +643,9 @@ def main() -> int:
     ap.add_argument("--serve-budget-gib", type=float, default=192.0)
     ap.add_argument("--small-workloads", action="store_true",
                     help="also time the 1D (1024 points) and 2D (1024^2) workloads and their oracle")
-    ap.add_argument("--mixed-radix", type=str, default="",
-                    help="comma-separated 7-smooth axis lengths: also time the 3D workload on those cubes")
+    ap.add_argument("--mixed-radix", type=str, default="480",
+                    help="comma-separated 7-smooth axis lengths: also time the 3D workload on those cubes "
+                         "('' to skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--summary-precision", choices=("all", "c64", "c128"), default="all",

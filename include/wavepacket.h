@@ -389,10 +389,11 @@ typedef struct wp_batch wp_batch;
  * they must outlive it, and while it exists they should be advanced only
  * through it.  Work is ordered on `stream` (hipStream_t or NULL).  Each
  * member's result equals its own wp_propagate result (same kernels, same
- * reduction order).  The batch's work is ordered on `stream` only: work
- * queued on members' own streams must be complete or on the same stream.
- * Errors: WP_EINVAL (count 0, NULL, a member in K-V-K order),
- * WP_EUNSUPPORTED (a member with a length that is not a power of two),
+ * reduction order).  Members on grids with a length that is not a power of
+ * two are not grouped: each takes the launches wp_propagate would make,
+ * within the batch's work.  The batch's work is ordered on `stream` only:
+ * work queued on members' own streams must be complete or on the same
+ * stream.  Errors: WP_EINVAL (count 0, NULL, a member in K-V-K order),
  * WP_ENOMEM, WP_EDEVICE. */
 wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_batch **out);
 

@@ -1530,6 +1530,9 @@ struct wp_batch {
   std::vector<PassGroup> groups;
   std::vector<GroupSpec> specs;
   std::vector<Group1D> groups1d;
+  // Members on mixed-length grids: advanced by their own schedule (the
+  // launches wp_propagate makes), ordered within the batch's work.
+  std::vector<int> solo;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint32_t exec_steps = 0;
@@ -1705,8 +1708,6 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
   if (!sims || count == 0) return WP_EINVAL;
   for (uint32_t i = 0; i < count; ++i)
     if (!sims[i] || sims[i]->order != WP_ORDER_VKV) return WP_EINVAL;
-  for (uint32_t i = 0; i < count; ++i)
-    if (sims[i]->mixed) return WP_EUNSUPPORTED;
   wp_batch *b = new (std::nothrow) wp_batch();
   if (!b) return WP_ENOMEM;
   b->sims.assign(sims, sims + count);
@@ -1739,6 +1740,10 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
     t0[i] = s->t0;
     dt[i] = s->g.dt;
     steps[i] = (int64_t)s->step;
+    if (s->mixed) {
+      b->solo.push_back((int)i);
+      continue;
+    }
     if (s->g.ndim == 1 && !s->split) {
       members1d[{s->prec, s->lg[0]}].push_back((int)i);
       continue;
@@ -1807,7 +1812,7 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
   for (size_t j = 0, gi = 0; e == hipSuccess && gi < b->groups1d.size(); ++gi)
     for (int i : members1d[{b->groups1d[gi].prec, b->groups1d[gi].lgN}])
       a1d[j++].time.step_dev = b->d_step + count + i;
-  if (e == hipSuccess && !b->groups1d.empty() && !b->groups.empty()) {
+  if (e == hipSuccess && (!b->groups1d.empty() || !b->solo.empty()) && !b->groups.empty()) {
     e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
@@ -1862,6 +1867,16 @@ wp_status wp_batch_propagate(wp_batch *b, uint64_t nsteps) {
   for (const Group1D &g : b->groups1d) {
     if (e != hipSuccess) break;
     e = wp::launch_solve1d_batch(g.prec, g.lgN, b->d_args1d + g.off, (int)g.count, (int64_t)nsteps, st1d);
+  }
+  // Mixed-length members: their own schedule, on the same stream as the 1D
+  // solvers.
+  for (int i : b->solo) {
+    if (e != hipSuccess) break;
+    wp_sim *s = b->sims[i];
+    const hipStream_t own = s->stream;
+    s->stream = st1d;
+    e = run_schedule(s, nsteps, [](int, auto &&fn) { return fn(); });
+    s->stream = own;
   }
   // 2D/3D members: open (potential half step at t_n and forward transform of
   // the first axis), nsteps-1 steady steps, and a final step closing with the

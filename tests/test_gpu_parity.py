@@ -197,13 +197,37 @@ def test_paul_trap_mixed_grid(S, W, oracle_mod, precision):
     assert rel_l2(got, ref) <= TOL[precision]
 
 
-def test_mixed_batch_rejected(S, W):
-    p = W.modulated_trap_2d(n=4, steps=0, precision="c64")
-    p.grid.n = [6, 10]
-    s = S.from_problem(p)
-    with pytest.raises(S.WavepacketError):
-        S.Batch([s])
-    s.close()
+@pytest.mark.parametrize("graph_steps", [0, 4])
+def test_mixed_members_in_a_batch(S, W, graph_steps):
+    """Members on mixed-length grids (1D, 2D, 3D, both precisions) advance in
+    a batch beside power-of-two members with their own launches: every
+    result equals its own wp_propagate result bit for bit."""
+    probs = []
+    p = W.modulated_trap_2d(n=4, steps=0, precision="c64", half_width=8.0)
+    p.grid.n = [60, 72]
+    probs.append(p)
+    p = W.softcore_3d(n=4, steps=0, precision="c128", half_width=5.0)
+    p.grid.n = [24, 20, 30]
+    p.t0 = 9.0
+    probs.append(p)
+    probs.append(W.driven_ho_1d(n=1000, steps=0, precision="c64"))
+    probs.append(W.modulated_trap_2d(n=64, steps=0, precision="c64", half_width=8.0))
+    probs.append(W.driven_ho_1d(n=512, steps=0, precision="c128"))
+    sims = [S.from_problem(q) for q in probs]
+    refs = [S.from_problem(q) for q in probs]
+    b = S.Batch(sims, graph_steps=graph_steps)
+    b.propagate(11)
+    b.propagate(6)
+    for r in refs:
+        r.propagate(11)
+        r.propagate(6)
+    for q, x, r in zip(probs, sims, refs):
+        prec = "c128" if q.precision == "c128" else "c64"
+        assert np.array_equal(x.get_state(prec), r.get_state(prec)), q.name
+        assert x.time() == r.time()
+    b.close()
+    for x in sims + refs:
+        x.close()
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
