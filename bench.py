@@ -253,6 +253,19 @@ def batch_bench(S, W, count: int, steps: int, graph_steps: int, ref_solves: int,
             "max_rel_l2_vs_fp64": max(errs)}
 
 
+def sweep_counts(count: int, warm: int, rates, capacity: float, limit_s: float):
+    """Requests per arrival rate for a sweep: a stream at rate f * capacity
+    takes about (warm + count) / (f * capacity) seconds; if the whole sweep
+    would take longer than limit_s (> 0), count and warm shrink by the same
+    factor (at least 100 measured and 10 warm-up requests).  Returns (count,
+    warm, projected seconds of the asked counts)."""
+    projected = sum((warm + count) / (f * capacity) for f in rates)
+    if limit_s > 0 and projected > limit_s:
+        scale = limit_s / projected
+        count, warm = max(100, int(count * scale)), max(10, int(warm * scale))
+    return count, warm, projected
+
+
 def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int, graph_steps: int,
                 budget_gib: float, ref_count: int, sweep_seconds: float = 0.0):
     """The serving workload: Poisson request streams (60% 1D 2^10..2^16, 30%
@@ -281,10 +294,7 @@ def serve_bench(S, W, V, count: int, warm: int, rates, cap_count: int, tick: int
     mean_work = float(np.mean([r.problem.grid.points() * r.problem.steps for r in mix]))
     C = cap["site_steps_per_s"] / mean_work
     asked = (count, warm)
-    projected = sum((warm + count) / (f * C) for f in rates)
-    if sweep_seconds > 0 and projected > sweep_seconds:
-        scale = sweep_seconds / projected
-        count, warm = max(100, int(count * scale)), max(10, int(warm * scale))
+    count, warm, projected = sweep_counts(count, warm, rates, C, sweep_seconds)
     runs = []
     for i, f in enumerate(rates):
         reqs = W.serving_stream(warm + count, f * C, seed=1306 + 1 + i)
