@@ -18,6 +18,10 @@ pytestmark = pytest.mark.gpu
 TOL = {"c128": 1e-10, "c64": 1e-4, "c64x": 1e-4}
 
 
+def shape_id(shape):
+    return "x".join(str(n) for n in shape)
+
+
 @pytest.fixture(scope="module")
 def S():
     from paper_1306_3247_amd import sim
@@ -250,7 +254,7 @@ def test_driven_ho_1d_full_length(S, W, oracle_mod):
 # the contiguous last axis (the kinetic pass), with full and partial tiles.
 @pytest.mark.parametrize("shape", [(2, 2), (4, 8), (16, 256), (128, 32), (64, 64), (8, 4096), (4096, 4),
                                    (512, 8), (512, 32), (1024, 8), (1024, 2), (8, 512), (2, 1024),
-                                   (16, 1024), (2048, 4), (4, 2048), (256, 16), (32, 128)])
+                                   (16, 1024), (2048, 4), (4, 2048), (256, 16), (32, 128)], ids=shape_id)
 def test_2d_random_state(S, W, oracle_mod, shape, order, precision):
     prob = W.modulated_trap_2d(n=4, steps=5, precision=precision)
     prob.grid.n = list(shape)
@@ -262,12 +266,13 @@ def test_2d_random_state(S, W, oracle_mod, shape, order, precision):
 
 @pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
 @pytest.mark.parametrize("order", ["vkv", "kvk"])
-# 512 and 1024 points on each of the three axes: the first-axis potential
+# 512 to 4096 points on each of the three axes: the first-axis potential
 # pass (padded planes), the middle-axis FFT pass (strided) and the last-axis
 # kinetic pass (contiguous), with full and partial tiles.
 @pytest.mark.parametrize("shape", [(2, 4, 2), (8, 8, 8), (16, 64, 8), (32, 32, 32), (4, 2, 1024),
                                    (512, 4, 8), (512, 2, 2), (1024, 2, 4), (8, 512, 4), (4, 1024, 2),
-                                   (8, 4, 512), (2, 8, 1024)])
+                                   (8, 4, 512), (2, 8, 1024), (2048, 2, 2), (2, 2048, 4), (4, 2, 2048),
+                                   (4096, 2, 2), (2, 4096, 2), (2, 2, 4096)], ids=shape_id)
 def test_3d_random_state(S, W, oracle_mod, shape, order, precision):
     prob = W.softcore_3d(n=4, steps=4, precision=precision, half_width=6.0)
     prob.grid.n = list(shape)
