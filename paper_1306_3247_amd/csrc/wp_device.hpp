@@ -160,8 +160,25 @@ constexpr int tw_count(int N) {
 // offset (an immediate in the LDS instruction).
 __device__ __forceinline__ constexpr int pad16(int i) { return i + (i >> 4); }
 
-template <int N, int VPT, int RAD, int LS, bool INV, class R, class Lds>
-__device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
+// Twiddle table in two places: its first TWL entries copied to LDS, the
+// whole table in global memory.  A stage whose entries all lie below TWL
+// reads the LDS copy, the others read global memory (through the caches).
+template <int TWL>
+struct TwSplit {
+  const cx<double> *lds, *glob;
+};
+// Entries of the stage with product LS (see tw_offset).
+template <int N, int LS>
+__device__ __forceinline__ const cx<double> *stage_tw(const cx<double> *tw) {
+  return tw + tw_offset<N>(LS);
+}
+template <int N, int LS, int TWL>
+__device__ __forceinline__ const cx<double> *stage_tw(const TwSplit<TWL> &tw) {
+  return (tw_offset<N>(LS) + 7 * LS <= TWL ? tw.lds : tw.glob) + tw_offset<N>(LS);
+}
+
+template <int N, int VPT, int RAD, int LS, bool INV, class R, class TW, class Lds>
+__device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const TW &tw, Lds lds) {
   constexpr int L = N / VPT;
   constexpr int M = VPT / RAD;  // butterflies per thread
   constexpr bool LAST = (LS * RAD == N);
@@ -173,7 +190,7 @@ __device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const cx<doubl
 #pragma unroll
     for (int r = 0; r < RAD; ++r) x[r] = v[m + r * M];
     if constexpr (LS > 1) {
-      const cx<double> *tws = tw + tw_offset<N>(LS) + k;
+      const cx<double> *tws = stage_tw<N, LS>(tw) + k;
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
         cx<double> w = tws[(r - 1) * LS];
@@ -208,8 +225,8 @@ __device__ __forceinline__ void lds_sync() {
   }
 }
 
-template <int N, int VPT, int RAD, int LS, bool INV, bool WAVE, class R, class Lds>
-__device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
+template <int N, int VPT, int RAD, int LS, bool INV, bool WAVE, class R, class TW, class Lds>
+__device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const TW &tw, Lds lds) {
   constexpr int L = N / VPT;
   fft_stage<N, VPT, RAD, LS, INV>(v, t, tw, lds);
   if constexpr (LS * RAD < N) {
@@ -230,8 +247,8 @@ __device__ __forceinline__ void fft_stages(cx<R> (&v)[VPT], int t, const cx<doub
 // reference.  WAVE (see lds_sync): each line lies within one wavefront, and
 // the caller has already synchronised the workgroup after any LDS it fills
 // together (twiddles, tables).
-template <int N, int VPT, bool INV, bool WAVE = false, class R, class Lds>
-__device__ __forceinline__ void line_fft(cx<R> (&v)[VPT], int t, const cx<double> *tw, Lds lds) {
+template <int N, int VPT, bool INV, bool WAVE = false, class R, class TW, class Lds>
+__device__ __forceinline__ void line_fft(cx<R> (&v)[VPT], int t, const TW &tw, Lds lds) {
   if constexpr (N > 8) lds_sync<WAVE>();
   fft_stages<N, VPT, fft_shape<N, VPT>::R0, 1, INV, WAVE>(v, t, tw, lds);
 }

@@ -47,17 +47,29 @@ struct pass_cfg {
   // keeps 8 to stay within its registers.
   static constexpr int VPT0 = (ELEM == 8 && N >= 16 && KIND != PK_VS) ? 16 : (N < 8 ? N : 8);
   static constexpr int VPT = ((TUNE & 1) && VPT0 == 16) ? 8 : VPT0;
-  static constexpr int TGT = (TUNE & 2) ? 256 : 512;  // threads aimed at
+  // Strided lines of 2048 points and more: one workgroup of up to 1024
+  // threads per CU with most of the LDS, so that a tile spans more
+  // neighbouring lines (longer row segments per cache line).
+  static constexpr bool WIDE = STRIDED && N >= 2048 && TUNE == 0;
+  static constexpr int TGT = (TUNE & 2) ? 256 : (WIDE ? 1024 : 512);  // threads aimed at
   static constexpr int L = N / VPT;
   static constexpr bool EXCH = N > 8;  // more than one stage: exchanges through LDS
   // Padded line length (see pad16).
   static constexpr int NP = N >= 16 ? N + N / 16 : N;
+  // Twiddle entries copied to LDS: the whole table up to 512 points; for
+  // longer lines (default variant) those of every stage but the last, which
+  // then reads its entries through the caches.
   static constexpr bool TW_LDS = N <= 512;
-  static constexpr int TW_BYTES = 16 * tw_count(N);
-  static constexpr int TAB_BYTES = KIND == PK_K ? 16 * N : 0;  // kinetic factors
-  // At most 80 KiB of LDS per workgroup (two per CU), 52 KiB in variant 2.
-  static constexpr int BUDGET = ((TUNE & 2) ? 53248 : 81920) - 1024;
-  static constexpr int DATA_BUDGET = BUDGET - (TW_LDS ? TW_BYTES : 0) - TAB_BYTES;
+  static constexpr int TWL = TW_LDS ? tw_count(N) : (TUNE == 0 ? tw_offset<N>(N / 8) : 0);
+  static constexpr int TW_BYTES = 16 * TWL;
+  // Kinetic factors of the line axis: staged in LDS up to 1024 points; longer
+  // lines read them through the caches and leave the LDS to line data.
+  static constexpr bool KT_LDS = N <= 1024;
+  static constexpr int TAB_BYTES = (KIND == PK_K && KT_LDS) ? 16 * N : 0;
+  // At most 80 KiB of LDS per workgroup (two per CU), 52 KiB in variant 2,
+  // 156 KiB for WIDE.
+  static constexpr int BUDGET = ((TUNE & 2) ? 53248 : (WIDE ? 159744 : 81920)) - 1024;
+  static constexpr int DATA_BUDGET = BUDGET - TW_BYTES - TAB_BYTES;
   static constexpr int T_LDS = EXCH ? imax(1, pow2_floor(DATA_BUDGET / (NP * ELEM))) : 4096;
   static constexpr int T_THR = imax(1, TGT / L);
   // Strided lines: enough neighbouring lines that each row segment read is
@@ -78,7 +90,7 @@ struct pass_cfg {
   static constexpr int WAVES_TARGET = (TUNE & 2) ? imax(1, imin(4, 3 * THREADS / 256)) : imax(1, imin(4, THREADS / 128));
   // No more waves than the LDS of a CU (160 KiB) lets in, so that the
   // register budget is not cut for occupancy that cannot happen.
-  static constexpr int LDS_BYTES = DATA_BYTES + (TW_LDS ? TW_BYTES : 0) + TAB_BYTES + 64;
+  static constexpr int LDS_BYTES = DATA_BYTES + TW_BYTES + TAB_BYTES + 64;
   static constexpr int WAVES_LDS = imax(1, (163840 / LDS_BYTES) * ((THREADS + 63) / 64) / 4);
   static constexpr int WAVES_EU = imin(WAVES_TARGET, WAVES_LDS);
 };
@@ -130,8 +142,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
   constexpr int L = C::L, VPT = C::VPT, TILE = C::TILE, NT = C::THREADS;
 
   __shared__ __align__(16) unsigned char s_raw[C::DATA_BYTES > 0 ? C::DATA_BYTES : 16];
-  __shared__ cx<double> s_tw[C::TW_LDS ? tw_count(N) : 1];
-  __shared__ cx<double> s_ktab[KIND == PK_K ? N : 1];
+  __shared__ cx<double> s_tw[C::TWL > 0 ? C::TWL : 1];
+  __shared__ cx<double> s_ktab[KIND == PK_K && C::KT_LDS ? N : 1];
   cx<R> *s_data = reinterpret_cast<cx<R> *>(s_raw);
 
   const int tid = threadIdx.x;
@@ -164,10 +176,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
   }
 
-  if constexpr (C::TW_LDS)
-    for (int e = tid; e < tw_count(N); e += NT) s_tw[e] = a.tw[e];
-  const cx<double> *tw = C::TW_LDS ? (const cx<double> *)s_tw : a.tw;
-  if constexpr (KIND == PK_K) {
+  if constexpr (C::TWL > 0)
+    for (int e = tid; e < C::TWL; e += NT) s_tw[e] = a.tw[e];
+  const TwSplit<C::TWL> tw{s_tw, a.tw};
+  if constexpr (KIND == PK_K && C::KT_LDS) {
     for (int e = tid; e < N; e += NT) s_ktab[e] = a.ktab[a.axis][e];
     __syncthreads();
   }
@@ -244,9 +256,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     // Last-axis lines of at most 64 threads lie within one wavefront each;
     // the tables were shared after the barrier above.
     constexpr bool WAVE = !STRIDED && L <= 64;
+    const cx<double> *ktab = C::KT_LDS ? (const cx<double> *)s_ktab : a.ktab[a.axis];
     line_fft<N, VPT, false, WAVE>(v, t, tw, lds);
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(s_ktab[t + L * u], kl));
+    for (int u = 0; u < VPT; ++u) v[u] = mul_acc(v[u], cmul(ktab[t + L * u], kl));
     line_fft<N, VPT, true, WAVE>(v, t, tw, lds);
   } else {
     const double *s_coef = coef;  // uniform: scalar loads
