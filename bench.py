@@ -437,6 +437,20 @@ def mixed_radix(S, W, sizes, steps: int = 20, warmup: int = 5):
     for the transforms): site-steps/s in FP32 and FP64 state, one step being
     the same four-pass schedule run by the mixed-radix kernels (FP64
     arithmetic in both)."""
+    return cube_rates(S, W, sizes, steps, warmup)
+
+
+def large_grid(S, W, sizes, steps: int = 5, warmup: int = 2):
+    """The 3D soft-core workload at the same spacing (0.15625) on cubes far
+    beyond 512^3 that one device's memory still holds (2048^3: a 64 GiB FP32
+    or 128 GiB FP64 state, one at a time): site-steps/s in FP32 and FP64."""
+    import torch
+
+    torch.cuda.empty_cache()
+    return cube_rates(S, W, sizes, steps, warmup)
+
+
+def cube_rates(S, W, sizes, steps: int, warmup: int):
     import torch
 
     stream = torch.cuda.current_stream()
@@ -455,6 +469,8 @@ def mixed_radix(S, W, sizes, steps: int = 20, warmup: int = 5):
             e1.synchronize()
             ms = e0.elapsed_time(e1) / steps
             s.close()
+            del s
+            torch.cuda.empty_cache()
             row[prec] = {"ms_per_step": round(ms, 4), "site_steps_per_s": n ** 3 / (ms / 1e3),
                          "bytes_frac_of_hbm_peak_4pass": round(4 * 2 * BYTES_PER_POINT[prec] * n ** 3 /
                                                                (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -656,6 +672,9 @@ def main() -> int:
     ap.add_argument("--mixed-radix", type=str, default="480",
                     help="comma-separated 7-smooth axis lengths: also time the 3D workload on those cubes "
                          "('' to skip)")
+    ap.add_argument("--large-grid", type=str, default="2048",
+                    help="comma-separated power-of-two axis lengths: also time the 3D workload on those cubes, "
+                         "one state at a time ('' to skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--summary-precision", choices=("all", "c64", "c128"), default="all",
@@ -786,6 +805,8 @@ def main() -> int:
         out["small_workloads"] = small_workloads(S, W, not args.no_cpu_baseline)
     if args.mixed_radix:
         out["mixed_radix"] = mixed_radix(S, W, [int(x) for x in args.mixed_radix.split(",") if x])
+    if args.large_grid:
+        out["large_grid"] = large_grid(S, W, [int(x) for x in args.large_grid.split(",") if x])
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["oracle_parity"] = cpu_baseline(S, W.softcore_3d(n=args.n, precision="c128"),
                                                                  args.cpu_seconds)

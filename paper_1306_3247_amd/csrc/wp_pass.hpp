@@ -164,8 +164,12 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
   const int64_t ustep = (int64_t)L * lstride;
   const uint32_t ops = a.ops;
 
+  // Non-temporal stores only where a workgroup writes whole cache lines: a
+  // line split between two workgroups is written twice and should meet its
+  // other half in L2.
+  constexpr uint32_t NT_OK = C::PAIR ? (uint32_t)OP_LOAD_NT : (OP_LOAD_NT | OP_STORE_NT);
   cx<R> v[VPT];
-  if (valid && (ops & OP_LOAD_NT)) {
+  if (valid && (ops & OP_LOAD_NT & NT_OK)) {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = load_nt_as<R>(pt + u * ustep);
   } else if (valid) {
@@ -382,7 +386,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     }
   }
 
-  if (valid && (ops & OP_STORE_NT)) {
+  if (valid && (ops & OP_STORE_NT & NT_OK)) {
 #pragma unroll
     for (int u = 0; u < VPT; ++u) store_nt_from(pt + u * ustep, v[u]);
   } else if (valid) {
