@@ -46,6 +46,11 @@ def fused_case(W, which, precision):
         prob = W.softcore_3d(n=64, steps=0, precision=precision, half_width=5.0)
         prob.t0 = 9.0
         return prob, 1, 7
+    if which == "3d_long":
+        prob = W.softcore_3d(n=8, steps=0, precision=precision, half_width=5.0)
+        prob.grid.n = [2048, 4, 8]  # 2048-point first-axis lines: one wide workgroup per CU
+        prob.t0 = 9.0
+        return prob, 1, 3
     prob = W.softcore_3d(n=128, steps=0, precision=precision, half_width=10.0)
     prob.t0 = 9.0
     return prob, 8, 5
@@ -58,7 +63,7 @@ def close(got, ref, keys, rel):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128", "c64x"])
-@pytest.mark.parametrize("which", ["2d", "2d_wide", "2d_short", "2d_long", "3d", "3d_slabs"])
+@pytest.mark.parametrize("which", ["2d", "2d_wide", "2d_short", "2d_long", "3d", "3d_long", "3d_slabs"])
 def test_fused_moments_match_separate(S, W, which, precision):
     prob, slabs, nsteps = fused_case(W, which, precision)
     print(f"observe case {which} {precision} grid {prob.grid.n[:prob.grid.ndim]}", flush=True)
