@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 
 import numpy as np
 import json
@@ -37,11 +38,20 @@ KERNEL_SOURCES = ("paper_1306_3247_amd/csrc/wp_kernels.hip", "paper_1306_3247_am
 BYTES_PER_POINT = {"c64": 8, "c128": 16}
 
 
+def code_only(text: str) -> str:
+    """C++ source without its comments, whitespace runs collapsed: what a
+    change to the kernels' code changes and a change to their comments does
+    not.  (String literals in the kernel sources hold no comment markers.)"""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -12,7 +12,8 @@
 //         along axis 1.
 // Workgroup shapes are chosen per (precision, N, layout, kind) so that two or
 // more workgroups fit in a CU's 160 KiB of LDS, letting one workgroup load
-// while another computes.
+// while another computes; strided lines of 2048 points and more trade that
+// for wider tiles (one workgroup per CU, see pass_cfg::WIDE).
 #pragma once
 #include <type_traits>
 
