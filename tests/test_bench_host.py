@@ -132,3 +132,12 @@ def test_traffic_for_reads_the_committed_table():
         assert got == t["entries"]["softcore_3d_512:c64:axis0:t0"]["bytes_per_launch"]
     else:
         assert got is None
+
+
+def test_kernel_hash_ignores_comments_only():
+    code = "int f(int a) {\n  // twice\n  return 2 * a; /* doubled */\n}\n"
+    recommented = "int f(int a) {   // doubled\n  /* a block\n     comment */ return 2 * a;\n}\n"
+    changed = "int f(int a) {\n  // twice\n  return 3 * a;\n}\n"
+    assert bench.code_only(code) == bench.code_only(recommented)
+    assert bench.code_only(code) != bench.code_only(changed)
+    assert bench.code_only(code) == "int f(int a) { return 2 * a; }"
