@@ -677,7 +677,7 @@ def main() -> int:
     ap.add_argument("--serve-tick", type=int, default=250)
     ap.add_argument("--serve-graph-steps", type=int, default=16)
     ap.add_argument("--serve-budget-gib", type=float, default=192.0)
-    ap.add_argument("--small-workloads", action="store_true",
+    ap.add_argument("--small-workloads", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the 1D (1024 points) and 2D (1024^2) workloads and their oracle")
     ap.add_argument("--mixed-radix", type=str, default="480",
                     help="comma-separated 7-smooth axis lengths: also time the 3D workload on those cubes "
