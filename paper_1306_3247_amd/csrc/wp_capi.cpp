@@ -260,10 +260,32 @@ hipError_t copy_in(void *dst, const void *src, size_t bytes) {
   return e;
 }
 
+// Allocations whose failure the caller reports through its status: a
+// failed call also leaves its error in the runtime's per-thread last-error
+// slot, which a later successful launch (checked with hipGetLastError)
+// would otherwise report as its own.
+hipError_t dev_alloc(void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t host_alloc(void **p, size_t bytes) {
+  hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+  }
+  return e;
+}
+
 // Allocate and fill a device array (complete when this returns).
 template <class T>
 hipError_t upload(T **dst, const std::vector<T> &src) {
-  hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
+  hipError_t e = dev_alloc((void **)dst, sizeof(T) * src.size());
   if (e != hipSuccess) return e;
   return copy_in(*dst, src.data(), sizeof(T) * src.size());
 }
@@ -311,11 +333,8 @@ int storage_prec(const wp_sim *s) { return s->prec == WP_C128 ? WP_C128 : WP_C64
 // The state buffer is allocated on first use unless the caller bound one.
 hipError_t ensure_state(wp_sim *s) {
   if (s->psi) return hipSuccess;
-  hipError_t e = hipMalloc(&s->psi, s->psi_bytes);
-  if (e != hipSuccess) {
-    s->psi = nullptr;
-    return e;
-  }
+  hipError_t e = dev_alloc(&s->psi, s->psi_bytes);
+  if (e != hipSuccess) return e;
   s->psi_owned = true;
   return hipMemsetAsync(s->psi, 0, s->psi_bytes, s->stream);
 }
@@ -578,10 +597,10 @@ wp_status wp_create(const wp_grid_desc *grid, const wp_potential_desc *pot, void
   if (e == hipSuccess) {
     int64_t b = (s->total + wp::kObsThreads - 1) / wp::kObsThreads;
     s->obs_blocks = (int)(b > 1024 ? 1024 : b);
-    e = hipMalloc((void **)&s->d_partials, sizeof(double) * 8 * (size_t)s->obs_blocks);
+    e = dev_alloc((void **)&s->d_partials, sizeof(double) * 8 * (size_t)s->obs_blocks);
   }
-  if (e == hipSuccess) e = hipMalloc((void **)&s->d_out8, sizeof(double) * 8);
-  if (e == hipSuccess) e = hipMalloc((void **)&s->d_coef, sizeof(double) * wp::CO_COUNT * wp::kCoefChunk);
+  if (e == hipSuccess) e = dev_alloc((void **)&s->d_out8, sizeof(double) * 8);
+  if (e == hipSuccess) e = dev_alloc((void **)&s->d_coef, sizeof(double) * wp::CO_COUNT * wp::kCoefChunk);
   if (e == hipSuccess) wp_state_bytes(grid, &s->psi_bytes);
   s->slab_lg = default_slab_lg(s);
   if (e != hipSuccess) {
@@ -700,7 +719,7 @@ wp_status wp_set_state_gaussian(wp_sim *s, const double center[3], const double 
   hipError_t e = ensure_state(s);
   if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
   if (!s->d_gauss) {
-    e = hipMalloc((void **)&s->d_gauss, sizeof(cx<double>) * (s->g.n[0] + s->g.n[1] + s->g.n[2]));
+    e = dev_alloc((void **)&s->d_gauss, sizeof(cx<double>) * (s->g.n[0] + s->g.n[1] + s->g.n[2]));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_gauss, hipEventDisableTiming);
     if (e != hipSuccess) return state_fail(s, e, "set_state_gaussian");
   } else {
@@ -1021,7 +1040,7 @@ wp_status wp_autotune(wp_sim *s, uint32_t reps, double *ms) {
   (void)hipSetDevice(s->device);
   hipError_t e = ensure_state(s);
   // The candidates run on a copy of the state, which they transform.
-  if (e == hipSuccess && !s->scratch) e = hipMalloc(&s->scratch, s->psi_bytes);
+  if (e == hipSuccess && !s->scratch) e = dev_alloc(&s->scratch, s->psi_bytes);
   if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
   const int last = s->vdim - 1;
   struct Cls {
@@ -1213,7 +1232,7 @@ wp_status wp_store_reference(wp_sim *s) {
   if (!s) return WP_EINVAL;
   (void)hipSetDevice(s->device);
   hipError_t e = ensure_state(s);
-  if (e == hipSuccess && !s->ref) e = hipMalloc(&s->ref, s->psi_bytes);
+  if (e == hipSuccess && !s->ref) e = dev_alloc(&s->ref, s->psi_bytes);
   if (e == hipSuccess) e = hipMemcpyAsync(s->ref, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
   if (e != hipSuccess) return state_fail(s, e, "store_reference");
   s->err.clear();
@@ -1261,7 +1280,7 @@ wp_status wp_observables(wp_sim *s, uint32_t mask, double *out) {
   if (e == hipSuccess) e = hipMemcpyAsync(sums, s->d_out8, sizeof(sums), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e == hipSuccess && energy) {
-    if (!s->scratch) e = hipMalloc(&s->scratch, s->psi_bytes);
+    if (!s->scratch) e = dev_alloc(&s->scratch, s->psi_bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, s->stream);
     for (int d = 0; d < s->vdim && e == hipSuccess; ++d) {
       wp::PassArgs p = pass_args(s, d, wp::OP_FWD);
@@ -1421,7 +1440,7 @@ wp_status wp_propagate_observe(wp_sim *s, uint64_t nsteps, uint32_t mask, double
       s->d_mpart = nullptr;
       s->mpart_rows = 0;
     }
-    if (e == hipSuccess) e = hipMalloc((void **)&s->d_mpart, sizeof(double) * 8 * (size_t)rows);
+    if (e == hipSuccess) e = dev_alloc((void **)&s->d_mpart, sizeof(double) * 8 * (size_t)rows);
     if (e != hipSuccess) return hip_fail(s, e, "propagate_observe");
     s->mpart_rows = rows;
   }
@@ -1732,7 +1751,7 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
   std::map<Key, std::vector<std::pair<int, int64_t>>> members;  // (solve, lines)
   std::map<std::pair<int, int>, std::vector<int>> members1d;    // (prec, lgN) -> solves
   if (e == hipSuccess) {
-    e = hipMalloc((void **)&b->d_coef, sizeof(double) * wp::CO_COUNT * (size_t)b->rows * count);
+    e = dev_alloc((void **)&b->d_coef, sizeof(double) * wp::CO_COUNT * (size_t)b->rows * count);
   }
   for (uint32_t i = 0; i < count && e == hipSuccess; ++i) {
     wp_sim *s = b->sims[i];
@@ -1805,8 +1824,8 @@ wp_status wp_batch_create(wp_sim *const *sims, uint32_t count, void *stream, wp_
       b->groups1d.push_back(g);
     }
   }
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_step, sizeof(int64_t) * 2 * count);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_step, sizeof(int64_t) * 2 * count, hipHostMallocDefault);
+  if (e == hipSuccess) e = dev_alloc((void **)&b->d_step, sizeof(int64_t) * 2 * count);
+  if (e == hipSuccess) e = host_alloc((void **)&b->h_step, sizeof(int64_t) * 2 * count);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_step, hipEventDisableTiming);
   // The 1D argument blocks read their step from the second set of counters.
   for (size_t j = 0, gi = 0; e == hipSuccess && gi < b->groups1d.size(); ++gi)
@@ -1955,7 +1974,7 @@ wp_status wp_batch_autotune(wp_batch *b, uint32_t reps) {
   for (int i = 0; i < count && e == hipSuccess; ++i) {
     if (!saved[i]) continue;
     wp_sim *s = b->sims[i];
-    if (!s->scratch) e = hipMalloc(&s->scratch, s->psi_bytes);
+    if (!s->scratch) e = dev_alloc(&s->scratch, s->psi_bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(s->scratch, s->psi, s->psi_bytes, hipMemcpyDeviceToDevice, b->stream);
   }
   // Waveform rows for the members' current steps (potential passes read row 0).
