@@ -160,7 +160,9 @@ wp_status wp_workspace_bytes(const wp_grid_desc *grid, uint64_t *bytes);
  * set-up of `initialize_potential`, Section 3.2.2).  `stream` is a
  * hipStream_t or NULL.  The state is zero and the time 0 until a set_state
  * call; the state buffer itself is allocated on first use unless one is
- * bound with wp_bind_state.  Axis lengths: powers of two (the fast
+ * bound with wp_bind_state (if it does not fit in device memory, that first
+ * call returns WP_ENOMEM and the handle stays valid: bind memory or
+ * destroy it).  Axis lengths: powers of two (the fast
  * kernels), or on grids where some length is not a power of two, lengths
  * with prime factors 2, 3, 5 and 7 only (the sizes Section 3.2.1 advises
  * for nx, ny, nz of struct `parameters`),
