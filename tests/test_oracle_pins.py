@@ -220,13 +220,17 @@ def test_waveform_special_values(oracle_mod):
     assert oracle_mod.wave_eval(s, (math.pi / 2 - 0.1) / 2) == pytest.approx(4.0, abs=1e-14)
 
 
+# Morse depth and range of CO (Section 4.1; tests/golden/co_morse_inputs.txt)
+CO_MORSE_D, CO_MORSE_A = 0.4076, 1.230211
+
+
 def test_potential_special_values(oracle_mod):
     # Morse (Section 4.1): zero at xe, D far out; soft-core -Z/sqrt(eps2) at r = 0.
     g = W.Grid(1, [8], [2.0], [2.0 + 8 * 4.0])
-    pot = W.Potential(v0_kind="morse", v0_par=(0.4076, 1.230211, 2.0, 0.0))
+    pot = W.Potential(v0_kind="morse", v0_par=(CO_MORSE_D, CO_MORSE_A, 2.0, 0.0))
     pot.s = W.const(1.0)
     V = oracle_mod.potential(g, pot, 0.0)
-    assert V[0] == 0.0 and abs(V[-1] - 0.4076) < 1e-12
+    assert V[0] == 0.0 and abs(V[-1] - CO_MORSE_D) < 1e-12
     g3 = W.Grid(3, [4, 4, 4], [-2.0] * 3, [2.0] * 3)
     sc = W.Potential(v0_kind="softcore", v0_par=(2.0, 0.25, 0, 0))
     sc.s = W.const(1.0)
