@@ -313,6 +313,56 @@ def test_ground_state_stationary_and_phase(oracle_mod):
     assert abs(np.angle(ov * np.exp(1j * 0.5 * 5.0))) <= 1e-4  # t = 5
 
 
+def softcore_ground_state(n, hw, mass, hbar):
+    """Lowest eigenpair of the discrete Hamiltonian of the 3D soft-core atom
+    (V = -1/sqrt(r^2 + 1), the 512^3 workload's static part) on an n^3
+    periodic grid: kinetic energy hbar^2 |k|^2 / 2m applied through numpy's
+    FFT with numpy's frequency grid, V from its formula, lowest eigenvalue
+    by scipy's Lanczos solver.  Nothing here is the oracle's."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+
+    dx = 2.0 * hw / n
+    x = -hw + np.arange(n) * dx
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    V = -1.0 / np.sqrt(X ** 2 + Y ** 2 + Z ** 2 + 1.0)
+    k = 2.0 * np.pi * np.fft.fftfreq(n, d=dx)
+    T = hbar ** 2 * (k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2) / (2.0 * mass)
+
+    def apply(v):
+        f = v.reshape(n, n, n)
+        return (np.fft.ifftn(T * np.fft.fftn(f)).real + V * f).ravel()
+
+    E, vecs = eigsh(LinearOperator((n ** 3, n ** 3), matvec=apply, dtype=float), k=1, which="SA", tol=1e-13)
+    phi = vecs[:, 0].reshape(n, n, n).astype(complex)
+    return E[0], phi / np.sqrt(np.sum(np.abs(phi) ** 2) * dx ** 3)
+
+
+def test_softcore_3d_eigenstate_stationary(oracle_mod):
+    """The soft-core atom in 3D with non-unit hbar and m: its discrete ground
+    state stays put under the oracle's steps (|<phi0|psi(t)>| = 1 to
+    rounding) and its phase advances as -E0 t / hbar up to the splitting
+    error, which falls as dt^2 (ratio 4 per halving).  With the soft-core
+    sign flipped the overlap moves by O(1)."""
+    n, hw, mass, hbar = 16, 8.0, 1.3, 0.9
+    E0, phi = softcore_ground_state(n, hw, mass, hbar)
+    pot = W.Potential(v0_kind="softcore", v0_par=(1.0, 1.0, 0.0, 0.0))
+    pot.s = W.const(1.0)
+    errs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        steps = int(round(0.5 / dt))
+        g = W.Grid(3, [n] * 3, [-hw] * 3, [hw] * 3, mass=mass, hbar=hbar, dt=dt)
+        ov = oracle_mod.inner(g, phi, oracle_mod.propagate(g, pot, phi, steps))
+        assert abs(abs(ov) - 1.0) <= 1e-12
+        errs.append(abs(np.angle(ov * np.exp(1j * E0 * steps * dt / hbar))))
+    assert errs[0] <= 1e-7
+    assert 3.6 <= errs[0] / errs[1] <= 4.4 and 3.6 <= errs[1] / errs[2] <= 4.4
+    flipped = W.Potential(v0_kind="softcore", v0_par=(-1.0, 1.0, 0.0, 0.0))
+    flipped.s = W.const(1.0)
+    g = W.Grid(3, [n] * 3, [-hw] * 3, [hw] * 3, mass=mass, hbar=hbar, dt=2e-3)
+    ov = oracle_mod.inner(g, phi, oracle_mod.propagate(g, flipped, phi, 250))
+    assert abs(abs(ov) - 1.0) > 1e-2
+
+
 # --- invariants ----------------------------------------------------------------
 
 
