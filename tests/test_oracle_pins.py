@@ -363,6 +363,44 @@ def test_softcore_3d_eigenstate_stationary(oracle_mod):
     assert abs(abs(ov) - 1.0) > 1e-2
 
 
+def test_morse_levels_and_ground_state_stationary(oracle_mod):
+    """CO of Section 4.1 with its printed inputs (tests/golden): the lowest
+    levels of the discrete Hamiltonian (dense, spectral kinetic term built
+    with numpy's FFT) equal Morse's closed form E_v = hbar w (v + 1/2) -
+    (hbar w (v + 1/2))^2 / 4D, w = a sqrt(2D/m); the printed laser frequency
+    lies within 1 % of E1 - E0 (the paper calls the pulse resonant with that
+    transition); and the oracle keeps the discrete ground state stationary,
+    its phase advancing as -E0 t with an error falling as dt^2."""
+    import scipy.linalg
+    from test_golden_inputs import read_golden
+
+    gi = read_golden("co_morse_inputs.txt")
+    m, D, a, xe = gi["reduced_mass_au"], gi["D_au"], gi["a_au"], gi["xe_au"]
+    w = a * math.sqrt(2.0 * D / m)
+    level = [w * (v + 0.5) - (w * (v + 0.5)) ** 2 / (4.0 * D) for v in range(3)]
+    n, lo, hi = 512, gi["grid_lo_au"], gi["grid_hi_au"]
+    dx = (hi - lo) / n
+    x = lo + np.arange(n) * dx
+    k = 2.0 * np.pi * np.fft.fftfreq(n, d=dx)
+    kinetic = np.fft.ifft((k ** 2 / (2.0 * m))[:, None] * np.fft.fft(np.eye(n), axis=0), axis=0).real
+    E, U = scipy.linalg.eigh(kinetic + np.diag(D * (1.0 - np.exp(-a * (x - xe))) ** 2))
+    for v in range(3):
+        assert E[v] == pytest.approx(level[v], rel=1e-12)
+    assert abs(gi["omega_au"] / (level[1] - level[0]) - 1.0) <= 0.01
+    phi = U[:, 0].astype(complex) / math.sqrt(dx)
+    pot = W.Potential(v0_kind="morse", v0_par=(D, a, xe, 0.0))
+    pot.s = W.const(1.0)
+    errs = []
+    for dt in (2.0, 1.0, 0.5):
+        steps = int(round(200.0 / dt))
+        g = W.Grid(1, [n], [lo], [hi], mass=m, dt=dt)
+        ov = oracle_mod.inner(g, phi, oracle_mod.propagate(g, pot, phi, steps))
+        assert abs(abs(ov) - 1.0) <= 1e-9
+        errs.append(abs(np.angle(ov * np.exp(1j * E[0] * steps * dt))))
+    assert errs[0] <= 1e-4
+    assert 3.6 <= errs[0] / errs[1] <= 4.4 and 3.6 <= errs[1] / errs[2] <= 4.4
+
+
 # --- invariants ----------------------------------------------------------------
 
 
