@@ -48,3 +48,31 @@ def test_fp32_norm_bias_per_step(S, W, n, precision):
     print(f"{n}^3 {precision}: norm slope {slope:.2e} per step, mean change {total:.2e} per step")
     assert abs(slope) < 2e-9
     assert abs(total) < 2e-9
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64", "c64x"])
+def test_softcore_ground_state_stationary(S, W, precision):
+    """The soft-core atom's discrete ground state (lowest eigenvector of the
+    spectral Hamiltonian, from scipy's Lanczos solver with numpy's FFT: no
+    part of the library or the oracle) on a 32^3 grid with hbar = 0.9 and
+    m = 1.3 stays put under the GPU's steps: the overlap keeps modulus 1 (to
+    rounding of the state's precision) and its phase advances as
+    -E0 t / hbar up to the splitting's O(dt^2) error."""
+    from test_oracle_pins import softcore_ground_state
+
+    n, hw, mass, hbar, dt, steps = 32, 8.0, 1.3, 0.9, 2e-3, 500
+    E0, phi = softcore_ground_state(n, hw, mass, hbar)
+    g = W.Grid(3, [n] * 3, [-hw] * 3, [hw] * 3, mass=mass, hbar=hbar, dt=dt)
+    pot = W.Potential(v0_kind="softcore", v0_par=(1.0, 1.0, 0.0, 0.0))
+    pot.s = W.const(1.0)
+    s = S.Simulation(g, pot, precision)
+    s.set_state(phi)
+    s.propagate(steps)
+    psi = s.get_state("c128")
+    s.close()
+    ov = np.sum(np.conj(phi) * psi) * (2 * hw / n) ** 3
+    drift = abs(abs(ov) - 1.0)
+    phase = abs(np.angle(ov * np.exp(1j * E0 * steps * dt / hbar)))
+    print(f"soft-core ground state {precision}: |<phi|psi>| - 1 = {drift:.2e}, phase error {phase:.2e}")
+    assert drift <= (1e-12 if precision == "c128" else 1e-5)
+    assert phase <= (5e-8 if precision == "c128" else 1e-5)
