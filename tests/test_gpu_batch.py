@@ -28,7 +28,7 @@ def mixed_problems(W):
     out = []
     specs = [(1, 256, "c128"), (1, 1024, "c64"), (2, 64, "c128"), (2, 128, "c64"), (2, 256, "c64x"),
              (2, 128, "c128"), (3, 32, "c64"), (3, 16, "c128"), (2, 512, "c64"), (1, 2048, "c64x"),
-             (1, 16384, "c64"), (1, 65536, "c128")]
+             (1, 16384, "c64"), (1, 65536, "c128"), (2, 2048, "c64")]
     for i, (ndim, n, prec) in enumerate(specs):
         p = W.driven_trap(ndim, n, E0=rng.uniform(0.01, 0.2), omega=rng.uniform(0.5, 2.0),
                           center=rng.uniform(-3, 3, ndim), k=rng.uniform(-1, 1, ndim), steps=0,
