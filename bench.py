@@ -807,22 +807,34 @@ def main() -> int:
         if args.accuracy_steps > 0:
             out["accuracy"] = full_length_accuracy(S, W, args.n, args.accuracy_steps)
 
+    def leg(name, fn):
+        """A leg beside the headline: a Python-level failure in it (say, an
+        allocation the device cannot serve) is reported in its field and on
+        stderr instead of costing the whole line."""
+        try:
+            out[name] = fn()
+        except Exception as e:  # noqa: BLE001 - reported, not hidden
+            import traceback
+
+            traceback.print_exc()
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+
     if not args.no_batch:
-        out["batch"] = batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200,
-                                   tune_reps)
+        leg("batch", lambda: batch_bench(S, W, args.batch_solves, args.batch_steps, args.batch_graph_steps, 32, 200,
+                                         tune_reps))
     if not args.no_serve:
         from paper_1306_3247_amd import serve as V
 
         rates = [float(x) for x in args.serve_rates.split(",") if x]
-        out["serving"] = serve_bench(S, W, V, args.serve_requests, args.serve_warmup, rates,
-                                     args.serve_capacity_requests, args.serve_tick, args.serve_graph_steps,
-                                     args.serve_budget_gib, 20, args.serve_seconds)
+        leg("serving", lambda: serve_bench(S, W, V, args.serve_requests, args.serve_warmup, rates,
+                                           args.serve_capacity_requests, args.serve_tick, args.serve_graph_steps,
+                                           args.serve_budget_gib, 20, args.serve_seconds))
     if args.small_workloads:
-        out["small_workloads"] = small_workloads(S, W, not args.no_cpu_baseline)
+        leg("small_workloads", lambda: small_workloads(S, W, not args.no_cpu_baseline))
     if args.mixed_radix:
-        out["mixed_radix"] = mixed_radix(S, W, [int(x) for x in args.mixed_radix.split(",") if x])
+        leg("mixed_radix", lambda: mixed_radix(S, W, [int(x) for x in args.mixed_radix.split(",") if x]))
     if args.large_grid:
-        out["large_grid"] = large_grid(S, W, [int(x) for x in args.large_grid.split(",") if x])
+        leg("large_grid", lambda: large_grid(S, W, [int(x) for x in args.large_grid.split(",") if x]))
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["oracle_parity"] = cpu_baseline(S, W.softcore_3d(n=args.n, precision="c128"),
                                                                  args.cpu_seconds)
