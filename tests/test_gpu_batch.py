@@ -121,3 +121,33 @@ def test_zero_steps_are_no_ops(S, W):
     assert np.array_equal(s.get_state("c128"), before)
     assert s.time() == (p.t0 + 3 * p.grid.dt, 3)
     s.close()
+
+
+def test_graph_replays_each_match_eager(S, W):
+    """Every replay of the batch's captured step sequence gives the eager
+    result: three calls of 9 steps with 4-step graphs (two replays and the
+    direct first and last steps per call), the states read back to the host
+    and other work queued on the device between the calls, each compared bit
+    for bit with members stepped alone to the same step count."""
+    import torch
+
+    probs = [W.driven_trap(2, 128, 0.1, 1.3, [0.5, -0.2], [0.3, 0.0], steps=0, precision="c64"),
+             W.driven_trap(2, 256, 0.05, 0.7, [-1.0, 0.4], [0.0, -0.2], steps=0, precision="c128"),
+             W.softcore_3d(n=32, steps=0, precision="c64", half_width=5.0)]
+    probs[2].t0 = 9.0
+    alone = [S.from_problem(p) for p in probs]
+    sims = [S.from_problem(p) for p in probs]
+    b = S.Batch(sims, graph_steps=4)
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for call in range(3):
+        b.propagate(9)
+        scratch.add_(1.0)  # eager work of the program between replays
+        torch.cuda.synchronize()
+        for a, s in zip(alone, sims):
+            a.propagate(9)
+            assert np.array_equal(s.get_state("c128"), a.get_state("c128")), (call, s.precision)
+            assert s.time() == a.time()
+    b.close()
+    for s in alone + sims:
+        s.close()
+    assert float(scratch[0]) == 3.0
