@@ -197,7 +197,10 @@ void *wp_state_ptr(wp_sim *sim);
 /* Copy a host state (row-major, complex128, n0*n1*n2 points) to the device,
  * converting to the handle's precision, and set the time origin: after this
  * call the state is psi(t0) and the step counter is 0 (the role of
- * `initialize_wf`, Section 3.2.4).  Synchronises. */
+ * `initialize_wf`, Section 3.2.4).  An FP32 state is converted on the
+ * device, through a staging buffer of at most 64 MiB that the call
+ * allocates and frees.  Synchronises.  Errors: WP_EINVAL (NULL, t0 not
+ * finite), WP_ENOMEM, WP_EDEVICE. */
 wp_status wp_set_state(wp_sim *sim, const double *host_psi_c128, double t0);
 
 /* Set psi(t0) to the Gaussian of Section 4.2,
@@ -219,7 +222,10 @@ wp_status wp_set_order(wp_sim *sim, int32_t order);
 
 /* Copy the state at the current time to host memory as interleaved
  * complex128 (as_prec = WP_C128) or complex64 (WP_C64; WP_C64X is not a
- * valid output format).  Synchronises. */
+ * valid output format), row-major, n0*n1*n2 points.  In the other
+ * precision than the stored state's the conversion runs on the device,
+ * through a staging buffer of at most 64 MiB that the call allocates and
+ * frees.  Synchronises.  Errors: WP_EINVAL, WP_ENOMEM, WP_EDEVICE. */
 wp_status wp_get_state(wp_sim *sim, void *host_out, int32_t as_prec);
 
 /* FP64 observables of the current state at the current time (Table 3 and

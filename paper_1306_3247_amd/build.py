@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwavepacket.so")
 
 SOURCES = ["wp_kernels.hip", "wp_pass_c64.hip", "wp_pass_c64_t1.hip", "wp_pass_c64_t2.hip", "wp_pass_c64_t3.hip",
-           "wp_pass_c64x.hip", "wp_pass_c128.hip", "wp_pass_c128_t2.hip", "wp_gpass.hip", "wp_capi.cpp"]
+           "wp_pass_c64x.hip", "wp_pass_c128.hip", "wp_pass_c128_t2.hip", "wp_gpass.hip", "wp_stage.hip",
+           "wp_capi.cpp"]
 
 # Packed FP32 instructions are kept out of every kernel: ordinary float code
 # compiled with them enabled has produced silent wrong results on this chip.

@@ -15,6 +15,7 @@
 
 #include "../../include/wavepacket.h"
 #include "wp_internal.hpp"
+#include "wp_stage.hpp"
 
 using wp::cx;
 
@@ -658,6 +659,33 @@ hipError_t copy_state(const wp_sim *s, void *dst, const void *src, size_t elem, 
   return hipSuccess;
 }
 
+// Host <-> state copy that changes the precision: runs of up to 2^22 points
+// (64 MiB of complex128) go through a device staging buffer and are
+// converted there, so PCIe carries each point once in the host's precision
+// and the host does no per-point work.  The host side is contiguous, in
+// logical order.  Synchronises.
+hipError_t convert_copy(wp_sim *s, void *host, int host_prec, bool to_device) {
+  const size_t he = host_prec == WP_C128 ? 16 : 8;
+  const int64_t chunk = std::min<int64_t>(s->total, (int64_t)1 << 22);
+  void *stage = nullptr;
+  hipError_t e = dev_alloc(&stage, (size_t)chunk * he);
+  for (int64_t first = 0; e == hipSuccess && first < s->total; first += chunk) {
+    const int64_t n = std::min<int64_t>(chunk, s->total - first);
+    char *h = (char *)host + (size_t)first * he;
+    if (to_device) {
+      e = hipMemcpyAsync(stage, h, (size_t)n * he, hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess) e = wp::launch_stage_in(storage_prec(s), s->psi, s->gd, host_prec, stage, first, n, s->stream);
+    } else {
+      e = wp::launch_stage_out(storage_prec(s), s->psi, s->gd, host_prec, stage, first, n, s->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(h, stage, (size_t)n * he, hipMemcpyDeviceToHost, s->stream);
+    }
+  }
+  // The staging buffer is released only once nothing queued uses it.
+  const hipError_t es = hipStreamSynchronize(s->stream);
+  if (stage) (void)hipFree(stage);
+  return e != hipSuccess ? e : es;
+}
+
 wp_status wp_set_state(wp_sim *s, const double *host, double t0) {
   if (!s) return WP_EINVAL;
   if (!host) return fail(s, WP_EINVAL, "set_state: NULL host buffer");
@@ -669,17 +697,9 @@ wp_status wp_set_state(wp_sim *s, const double *host, double t0) {
     e = copy_state(s, s->psi, host, 16, true);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   } else {
-    std::vector<float> tmp;
-    try {
-      tmp.resize(2 * (size_t)s->total);
-    } catch (...) {
-      return fail(s, WP_ENOMEM, "set_state: host allocation failed");
-    }
-    for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)host[i];
-    e = copy_state(s, s->psi, tmp.data(), 8, true);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    e = convert_copy(s, const_cast<double *>(host), WP_C128, true);
   }
-  if (e != hipSuccess) return hip_fail(s, e, "set_state");
+  if (e != hipSuccess) return state_fail(s, e, "set_state");
   s->t0 = t0;
   s->step = 0;
   s->err.clear();
@@ -1194,22 +1214,10 @@ wp_status wp_get_state(wp_sim *s, void *host_out, int32_t as_prec) {
   if (as_prec == storage_prec(s)) {
     e = copy_state(s, host_out, s->psi, as_prec == WP_C128 ? 16 : 8, false);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  } else if (storage_prec(s) == WP_C64) {
-    std::vector<float> tmp(2 * (size_t)s->total);
-    e = copy_state(s, tmp.data(), s->psi, 8, false);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    double *o = (double *)host_out;
-    if (e == hipSuccess)
-      for (size_t i = 0; i < tmp.size(); ++i) o[i] = tmp[i];
   } else {
-    std::vector<double> tmp(2 * (size_t)s->total);
-    e = copy_state(s, tmp.data(), s->psi, 16, false);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    float *o = (float *)host_out;
-    if (e == hipSuccess)
-      for (size_t i = 0; i < tmp.size(); ++i) o[i] = (float)tmp[i];
+    e = convert_copy(s, host_out, as_prec, false);
   }
-  if (e != hipSuccess) return hip_fail(s, e, "get_state");
+  if (e != hipSuccess) return state_fail(s, e, "get_state");
   s->err.clear();
   return WP_OK;
 }
