@@ -115,3 +115,29 @@ def test_inner_takes_contiguous_phi(S, W, precision, n):
     o = s.observables(S.OBS_NORM | (1 << 11))
     assert o["autocorrelation"] == pytest.approx(o["norm"] ** 4, rel=1e-12)
     s.close()
+
+
+# Precision-changing transfers convert on the device in runs of 2^22 points:
+# grids of one run, of several with a ragged last one, padded and not.
+@pytest.mark.parametrize("precision,n", [("c64", [64, 32, 16]), ("c128", [32, 64, 8]), ("c64", [256, 128, 256]),
+                                         ("c64", [192, 128, 256]), ("c128", [256, 128, 160]), ("c64x", [96, 64, 48])])
+def test_transfers_across_precisions(S, W, precision, n):
+    prob = problem(W, precision, n)
+    s = S.from_problem(prob)
+    rng = np.random.default_rng(sum(n))
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    s.set_state(x)
+    stored = x.astype(np.complex64) if precision != "c128" else x
+    # the state as stored, read back in both precisions
+    assert np.array_equal(s.get_state("c128"), stored.astype(np.complex128))
+    assert np.array_equal(s.get_state("c64"), stored.astype(np.complex64))
+    # after steps: the converted read is the exact widening or rounding of
+    # the read in the stored precision
+    s.propagate(2)
+    same = s.get_state("c128" if precision == "c128" else "c64")
+    other = s.get_state("c64" if precision == "c128" else "c128")
+    s.close()
+    if precision == "c128":
+        assert np.array_equal(other, same.astype(np.complex64))
+    else:
+        assert np.array_equal(other, same.astype(np.complex128))
