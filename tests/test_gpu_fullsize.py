@@ -282,3 +282,24 @@ def test_softcore_512_slabs_and_cache_hints_bit_identical(S, W):
         out.append(s.get_state("c64"))
         s.close()
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_softcore_512_observe_fused_equals_separate(S, W, precision):
+    """At full size the closing pass's moments (16384 workgroup rows in FP32)
+    equal a propagation followed by a separate reduction, to the order of
+    FP64 summation, and the states are the same bits."""
+    prob = W.softcore_3d(n=512, steps=0, precision=precision)
+    prob.t0 = 9.5
+    a, b = S.from_problem(prob), S.from_problem(prob)
+    mask = S.OBS_NORM | S.OBS_MOMENTS
+    a.propagate(3)
+    want = a.observables(mask)
+    have = b.propagate_observe(3, mask)
+    same = np.array_equal(a.state_tensor().cpu().numpy(), b.state_tensor().cpu().numpy())
+    a.close()
+    b.close()
+    assert same
+    scale = max(1.0, max(abs(v) for v in want.values()))
+    for k, v in want.items():
+        assert abs(have[k] - v) <= 1e-13 * scale, (k, have[k], v)
