@@ -181,9 +181,20 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
   }
 
-  if constexpr (C::TWL > 0)
-    for (int e = tid; e < C::TWL; e += NT) s_tw[e] = a.tw[e];
-  const TwSplit<C::TWL> tw{s_tw, a.tw};
+  // FP32 passes with the whole table in LDS keep it as hi + lo pairs (the
+  // same 16 bytes per entry; see TwHiLo), the others as FP64.
+  constexpr bool HILO = std::is_same<R, float>::value && C::TW_LDS && C::TWL > 0;
+  using TwT = std::conditional_t<HILO, TwHiLo, TwSplit<C::TWL>>;
+  TwT tw;
+  if constexpr (HILO) {
+    float4 *s_tw4 = reinterpret_cast<float4 *>(s_tw);
+    for (int e = tid; e < C::TWL; e += NT) s_tw4[e] = hilo_of(a.tw[e]);
+    tw = TwHiLo{s_tw4};
+  } else {
+    if constexpr (C::TWL > 0)
+      for (int e = tid; e < C::TWL; e += NT) s_tw[e] = a.tw[e];
+    tw = TwSplit<C::TWL>{s_tw, a.tw};
+  }
   if constexpr (KIND == PK_K && C::KT_LDS) {
     for (int e = tid; e < N; e += NT) s_ktab[e] = a.ktab[a.axis][e];
     __syncthreads();
