@@ -217,18 +217,6 @@ template <int N, int LS, int TWL>
 __device__ __forceinline__ const cx<double> *stage_tw(const TwSplit<TWL> &tw) {
   return (tw_offset<N>(LS) + 7 * LS <= TWL ? tw.lds : tw.glob) + tw_offset<N>(LS);
 }
-// The same with the LDS part as hi + lo pairs (see TwHiLo): a stage reads
-// either float4 entries from LDS or FP64 ones through the caches.
-template <int TWL>
-struct TwSplitHiLo {
-  const float4 *lds;
-  const cx<double> *glob;
-};
-template <int N, int LS, int TWL>
-__device__ __forceinline__ auto stage_tw(const TwSplitHiLo<TWL> &tw) {
-  if constexpr (tw_offset<N>(LS) + 7 * LS <= TWL) return tw.lds + tw_offset<N>(LS);
-  else return tw.glob + tw_offset<N>(LS);
-}
 
 template <int N, int VPT, int RAD, int LS, bool INV, class R, class TW, class Lds>
 __device__ __forceinline__ void fft_stage(cx<R> (&v)[VPT], int t, const TW &tw, Lds lds) {

@@ -181,18 +181,15 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const double *coef,
     for (int u = 0; u < VPT; ++u) v[u] = cx<R>{0, 0};
   }
 
-  // FP32 passes keep the twiddles they copy to LDS as hi + lo pairs (the
-  // same 16 bytes per entry; see TwHiLo), FP64 passes as FP64; entries
-  // beyond the LDS copy are read as FP64 through the caches.
-  constexpr bool HILO = std::is_same<R, float>::value && C::TWL > 0;
-  using TwT = std::conditional_t<HILO, std::conditional_t<C::TW_LDS, TwHiLo, TwSplitHiLo<C::TWL>>,
-                                 TwSplit<C::TWL>>;
+  // FP32 passes with the whole table in LDS keep it as hi + lo pairs (the
+  // same 16 bytes per entry; see TwHiLo), the others as FP64.
+  constexpr bool HILO = std::is_same<R, float>::value && C::TW_LDS && C::TWL > 0;
+  using TwT = std::conditional_t<HILO, TwHiLo, TwSplit<C::TWL>>;
   TwT tw;
   if constexpr (HILO) {
     float4 *s_tw4 = reinterpret_cast<float4 *>(s_tw);
     for (int e = tid; e < C::TWL; e += NT) s_tw4[e] = hilo_of(a.tw[e]);
-    if constexpr (C::TW_LDS) tw = TwHiLo{s_tw4};
-    else tw = TwSplitHiLo<C::TWL>{s_tw4, a.tw};
+    tw = TwHiLo{s_tw4};
   } else {
     if constexpr (C::TWL > 0)
       for (int e = tid; e < C::TWL; e += NT) s_tw[e] = a.tw[e];
